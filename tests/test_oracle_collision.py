@@ -1,0 +1,284 @@
+"""Pins of the oracle's collision (sec. 2.2), equilibria (sec. 2.4, 5.2), streaming
+(eq. LbUpdateScheme) and hydrodynamic behaviour (Taylor-Green decay, sec. 5.1)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import lbm_workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
+
+CASES = [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
+         ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
+         ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")]
+
+
+def _general_rates(name, seed):
+    st = O.stencil(name)
+    rng = np.random.default_rng(seed)
+    om = rng.uniform(0.6, 1.9, st.q)
+    om[st.conserved] = 0
+    return om
+
+
+def _state(method, n=24, seed=0, noise=1e-3):
+    st = method.st
+    rng = np.random.default_rng(seed)
+    rho = 1 + 0.02 * rng.standard_normal(n)
+    u = rng.uniform(-0.06, 0.06, (n, 3))
+    if st.d == 2:
+        u[:, 2] = 0
+    feq = O.equilibrium_populations(method, rho, u)
+    return feq - method.f0 + noise * rng.standard_normal(feq.shape)
+
+
+def _forms(space):
+    return ["absolute", "zc_absolute"] + (["delta"] if space != "cumulant" else [])
+
+
+@pytest.mark.parametrize("name,space", CASES)
+def test_three_collision_forms_agree(name, space):
+    """eq. MrtUpdateGeneral, eq. MrtUpdateGeneralDeviationOnly and eq.
+    MrtUpdateAbsoluteFromZeroCentered are algebraically identical (sec. 2.2)."""
+    m = O.Method(name, space, _general_rates(name, 1))
+    df = _state(m)
+    outs = {}
+    for form in _forms(space):
+        if form == "absolute":
+            outs[form] = O.collide_cells(m, df + m.f0, form) - m.f0
+        else:
+            outs[form] = O.collide_cells(m, df, form)
+    ref = outs["zc_absolute"]
+    for form, v in outs.items():
+        np.testing.assert_allclose(v, ref, rtol=0, atol=1e-14, err_msg=form)
+
+
+def test_delta_equilibrium_rejected_for_cumulants():
+    m = O.Method("D3Q27", "cumulant", _general_rates("D3Q27", 2))
+    with pytest.raises(ValueError):
+        O.collide_cells(m, _state(m, n=2), "delta")
+
+
+@pytest.mark.parametrize("name,space", CASES)
+def test_equilibrium_is_fixed_point(name, space):
+    m = O.Method(name, space, _general_rates(name, 3))
+    df = _state(m, noise=0.0)
+    out = O.collide_cells(m, df, O.default_form(m))
+    np.testing.assert_allclose(out, df, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,space", CASES)
+def test_per_cell_conservation(name, space):
+    m = O.Method(name, space, _general_rates(name, 4))
+    st = m.st
+    df = _state(m)
+    out = O.collide_cells(m, df, O.default_form(m))
+    np.testing.assert_allclose(out.sum(axis=1), df.sum(axis=1), rtol=0, atol=1e-15)
+    xi = st.xi.astype(float)
+    np.testing.assert_allclose(out @ xi, df @ xi, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name,space", CASES)
+def test_zero_rates_identity_unit_rates_equilibrium(name, space):
+    st = O.stencil(name)
+    df = None
+    m0 = O.Method(name, space, np.zeros(st.q))
+    df = _state(m0)
+    np.testing.assert_allclose(O.collide_cells(m0, df, O.default_form(m0)), df, rtol=0, atol=1e-15)
+    om1 = np.ones(st.q)
+    om1[st.conserved] = 0
+    m1 = O.Method(name, space, om1)
+    out = O.collide_cells(m1, df, O.default_form(m1))
+    rho, u = O.macroscopic_from_delta(m1, df)
+    want = O.equilibrium_populations(m1, rho, u) - m1.f0
+    np.testing.assert_allclose(out, want, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_raw_equal_rates_is_bgk(name):
+    """Raw moments with one rate for every polynomial reduce to the single-relaxation-time
+    (BGK) operator f* = f + omega (f^eq - f) (sec. 1, SRT)."""
+    st = O.stencil(name)
+    om = np.full(st.q, 1.37)
+    m = O.Method(name, "raw", om)
+    df = _state(m)
+    out = O.collide_cells(m, df, "delta")
+    rho, u = O.macroscopic_from_delta(m, df)
+    feq = np.linalg.solve(st.M, O.raw_maxwellian_truncated(st, rho, u).T).T
+    want = df + 1.37 * (feq - m.f0 - df)
+    np.testing.assert_allclose(out, want, rtol=0, atol=4e-15)
+
+
+def test_worked_propagation_example():
+    """sec. 4.3: without a force the post-collision first-order raw moment is rho u_x."""
+    m = O.Method("D3Q27", "central", _general_rates("D3Q27", 5))
+    df = _state(m)
+    rho, u = O.macroscopic_from_delta(m, df)
+    out = O.collide_cells(m, df, "delta")
+    mx = (out + m.f0) @ m.st.xi[:, 0].astype(float)
+    np.testing.assert_allclose(mx, rho * u[:, 0], rtol=0, atol=1e-15)
+
+
+def test_regularized_cumulant_higher_orders_at_equilibrium():
+    """With every rate of order >= 3 equal to 1 the post-collision cumulants of order >= 3
+    vanish (their Maxwellian values), sec. 4.3."""
+    st = O.stencil("D3Q27")
+    m = O.Method("D3Q27", "cumulant", O.regularized_rates("D3Q27", 1.8))
+    df = _state(m)
+    out = O.collide_cells(m, df, "zc_absolute") + m.f0
+    rho = out.sum(axis=1)
+    u = (out @ st.xi.astype(float)) / rho[:, None]
+    kap = np.einsum("nji,ni->nj", O.central_matrix(st, u), out)
+    C = O.cumulants_from_central(st, kap, rho, u)
+    hi = [j for j, e in enumerate(st.exps) if sum(e) >= 3]
+    np.testing.assert_allclose(C[:, hi], 0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- shallow water (sec. 5.2)
+def test_swe_equilibrium_moments_and_typo_reading():
+    st = O.stencil("D2Q9")
+    rng = np.random.default_rng(7)
+    n, g = 10, 0.1
+    h = 1 + 0.2 * rng.random(n)
+    u = np.zeros((n, 3))
+    u[:, :2] = rng.uniform(-0.1, 0.1, (n, 2))
+    f = O.swe_equilibrium(st, h, u, g)
+    xi = st.xi.astype(float)
+    np.testing.assert_allclose(f.sum(axis=1), h, atol=1e-15)
+    np.testing.assert_allclose(f @ xi[:, :2], h[:, None] * u[:, :2], atol=1e-15)
+    for a in range(2):
+        for b in range(2):
+            s = (f * xi[:, a] * xi[:, b]).sum(axis=1)
+            want = g * h * h / 2 * (a == b) + h * u[:, a] * u[:, b]
+            np.testing.assert_allclose(s, want, atol=1e-15)
+    # the printed equation's -u.u/3 in f_i (i > 0) loses mass: sum f = h (1 - 5 u.u / 6)
+    uu = (u * u).sum(axis=1)
+    lam = np.where(np.abs(st.xi).sum(axis=1) == 1, 1.0, 0.25)
+    f_typo = f.copy()
+    f_typo[:, 1:] -= lam[None, 1:] * h[:, None] * uu[:, None] / 6
+    np.testing.assert_allclose(f_typo.sum(axis=1), h * (1 - 5 * uu / 6), atol=1e-15)
+
+
+def test_swe_lake_at_rest_is_fixed_point():
+    om = O.regularized_rates("D2Q9", 0.7)
+    m = O.Method("D2Q9", "central", om, equilibrium="swe", gravity=0.1)
+    h = np.full((1, 6, 5), 1.3)
+    u = np.zeros((3, 1, 6, 5))
+    df = O.init_equilibrium(m, h, u)
+    out = O.step(m, df, 3)
+    np.testing.assert_allclose(out, df, rtol=0, atol=1e-15)
+
+
+def test_dam_break_rate_golden():
+    g = json.load(open(GOLDEN))["dam_break_rate"]
+    dx = g["domain_m"] / g["cells"]
+    nu_lattice = g["nu_m2_per_s"] * g["dt_s"] / dx ** 2
+    om = O.viscosity_to_omega(nu_lattice)
+    assert round(om, g["printed_digits"]) == g["omega_s_approx"]
+    v = json.load(open(GOLDEN))["viscosity_relation"]
+    assert abs(O.viscosity_to_omega(v["nu"]) - v["omega"]) < 1e-15
+
+
+# ---------------------------------------------------------------- streaming (eq. LbUpdateScheme)
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+def test_streaming_moves_impulse_by_xi(name):
+    m = O.Method(name, "raw", np.zeros(O.stencil(name).q))
+    st = m.st
+    shape = (5, 4, 3) if st.d == 3 else (1, 4, 3)
+    for i in range(st.q):
+        f = np.zeros((st.q,) + shape)
+        f[i, 0, 1, 2] = 1.0
+        g = O.stream(m, f)
+        z = (0 + st.xi[i, 2]) % shape[0]
+        y = (1 + st.xi[i, 1]) % shape[1]
+        x = (2 + st.xi[i, 0]) % shape[2]
+        assert g[i, z, y, x] == 1.0 and g.sum() == 1.0
+
+
+def test_pure_streaming_returns_after_period():
+    """All rates 0: the collision is the identity up to the round-off of T^-1 T, and N steps
+    of periodic streaming on an N^3 box restore the initial state."""
+    name = "D3Q27"
+    m = O.Method(name, "central", np.zeros(27))
+    rng = np.random.default_rng(8)
+    df0 = 1e-3 * rng.standard_normal((27, 6, 6, 6))
+    out = O.step(m, df0, 6)
+    np.testing.assert_allclose(out, df0, rtol=0, atol=1e-15)
+
+
+# ---------------------------------------------------------------- hydrodynamics (sec. 5.1)
+def _tgv_amplitude(method, n, nz, u0, steps, every):
+    rho, u = W.tgv2d_fields(n, n, nz, u0=u0)
+    df = O.init_equilibrium(method, rho, u)
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    ref = np.cos(k * x)[None, :] * np.sin(k * x)[:, None]
+    amps = []
+    for t in range(0, steps + 1, every):
+        _, uu = O.macroscopic(method, df)
+        amps.append((uu[0, 0] * ref).sum() / (ref * ref).sum())
+        if t < steps:
+            df = O.step(method, df, every)
+    return np.array(amps)
+
+
+@pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
+def test_taylor_green_decay_rate_d2q9(space):
+    """u(t) = u0 exp(-2 nu k^2 t) (eq. TGA_init) with nu = c_s^2 (1/omega - 1/2); the fitted
+    rate on a 32^2 box at low Mach number is within 0.5 % of 2 nu k^2."""
+    omega = 1.2
+    om = O.regularized_rates("D2Q9", omega)
+    m = O.Method("D2Q9", space, om)
+    n, steps, every = 32, 200, 20
+    amps = _tgv_amplitude(m, n, 1, 1e-3, steps, every)
+    nu = O.omega_to_viscosity(omega)
+    k = 2 * math.pi / n
+    t = np.arange(0, steps + 1, every)
+    rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
+    assert abs(rate / (2 * nu * k * k) - 1) < 5e-3
+
+
+def test_taylor_green_second_order_convergence():
+    """The relative decay-rate error falls about fourfold per doubling of the resolution."""
+    omega = 1.2
+    m = O.Method("D2Q9", "central", O.regularized_rates("D2Q9", omega))
+    nu = O.omega_to_viscosity(omega)
+    errs = []
+    for n in (16, 32):
+        steps = int(round(0.2 * n * n / (4 * math.pi ** 2 * nu)))  # same diffusive time
+        every = max(1, steps // 10)
+        amps = _tgv_amplitude(m, n, 1, 1e-3, every * 10, every)
+        k = 2 * math.pi / n
+        t = np.arange(0, every * 10 + 1, every)
+        rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
+        errs.append(abs(rate / (2 * nu * k * k) - 1))
+    ratio = errs[0] / errs[1]
+    assert 3.0 < ratio < 5.5, (errs, ratio)
+
+
+def test_taylor_green_energy_decay_d3q27_cumulant():
+    """z-invariant Taylor-Green vortex on a D3Q27 cumulant box (32 x 32 x 1): the fitted
+    decay rate of E follows 4 nu k^2 (E/E0 = exp(-4 nu k^2 t), sec. 5.1) within 1 %;
+    mass and momentum stay at their initial values."""
+    omega = 1.0
+    m = O.Method("D3Q27", "cumulant", O.regularized_rates("D3Q27", omega))
+    n = 32
+    rho, u = W.tgv2d_fields(n, n, 1, u0=1e-3)
+    df = O.init_equilibrium(m, rho, u)
+    d0 = O.diagnostics(m, df)
+    nu = O.omega_to_viscosity(omega)
+    k = 2 * math.pi / n
+    every = 2
+    energies = [d0[4]]
+    for _ in range(9):
+        df = O.step(m, df, every)
+        energies.append(O.diagnostics(m, df)[4])
+    t = np.arange(10) * every
+    rate = -np.polyfit(t[1:], np.log(energies[1:]), 1)[0]
+    assert abs(rate / (4 * nu * k * k) - 1) < 1e-2
+    d = O.diagnostics(m, df)
+    assert abs(d[0] - d0[0]) < 1e-11 and np.abs(d[1:4] - d0[1:4]).max() < 1e-12
