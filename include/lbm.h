@@ -1,0 +1,230 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) zero-centred multiple-relaxation-time lattice
+ * Boltzmann library.
+ *
+ * The operations follow Hennig, Holzer, Ruede, "Advanced Automatic Code Generation for
+ * Multiple Relaxation-Time Lattice Boltzmann Methods" (arXiv 2211.02435):
+ *   - a method is a stencil, a storage format, a collision space with a polynomial basis,
+ *     one relaxation rate per basis polynomial and an equilibrium (sec. 3, configuration
+ *     space of the modelling front-end);
+ *   - one time step is the fused collide-and-stream update of eq. LbUpdateScheme (sec. 2.1)
+ *     with the collision of eq. MrtUpdateGeneralDeviationOnly (raw or central moments with
+ *     the delta-equilibrium) or eq. MrtUpdateAbsoluteFromZeroCentered (any space with the
+ *     absolute equilibrium), sec. 2.2, on zero-centred populations df = f - f0 (sec. 2.1);
+ *   - the collision-space transforms are the raw-moment Chimera transform (eq.
+ *     RawMomentChimeraTransform, sec. 4.1.1), the binomial Chimera transform between raw
+ *     and central moments (sec. 4.2) and the central-moment / cumulant relation of
+ *     eq. CumulantAndCentralMomentGenFuncs (sec. 4.2.1).
+ *
+ * Conventions (the paper fixes only xi_0 = 0):
+ *   Velocity order, opposite pairs adjacent (opp(i) = i+1 for odd i):
+ *     D2Q9 : (0,0) (1,0) (-1,0) (0,1) (0,-1) (1,1) (-1,-1) (1,-1) (-1,1)
+ *     D3Q27: (0,0,0); (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1);
+ *            (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+ *            (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1);
+ *            (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1)
+ *     D3Q19: the first 19 velocities of D3Q27.
+ *   Weights (background f0 for the Maxwellian equilibrium, f0 = M^-1 m0 = w, sec. 2.4):
+ *     D2Q9 4/9 1/9 1/36; D3Q19 1/3 1/18 1/36; D3Q27 8/27 2/27 1/54 1/216.  c_s^2 = 1/3,
+ *     rho0 = 1.  For the shallow-water equilibrium f0 = f^eq(h = 1, u = 0).
+ *   Polynomial basis, one relaxation rate per entry of `omegas`, in this order
+ *   (graded: every polynomial is homogeneous in one order):
+ *     D2Q9 (the basis of the shallow-water listing, sec. 5.2):
+ *       1, x, y, xy, x2-y2, x2+y2, xy2, x2y, x2y2
+ *     D3Q19: 1, x, y, z, xy, xz, yz, x2-y2, x2-z2, x2+y2+z2,
+ *            xy2+xz2, xy2-xz2, x2y+yz2, x2y-yz2, x2z+y2z, x2z-y2z,
+ *            x2y2-2x2z2+y2z2, x2y2+x2z2-2y2z2, x2y2+x2z2+y2z2
+ *     D3Q27: the first 16 of D3Q19, xyz, the three fourth-order combinations of D3Q19,
+ *            x2yz, xy2z, xyz2, xy2z2, x2yz2, x2y2z, x2y2z2
+ *     Rates of the conserved polynomials 1, x, y, z are ignored.
+ *   Equilibria: LBM_EQ_MAXWELLIAN is the continuous Maxwellian of sec. 2.4; its raw moments
+ *     are truncated at second order in u (sec. 4.3), its central moments and cumulants are
+ *     used exactly (they do not depend on u).  LBM_EQ_SHALLOW_WATER is the discrete D2Q9
+ *     equilibrium of Zhou (sec. 5.2) with the listing's -u.u/6 term; `gravity` is g.
+ *
+ * Memory layout of every field argument: SoA, x fastest.
+ *   cell(x, y, z) = (z * ny + y) * nx + x, ncells = nx * ny * nz
+ *   populations  df[i * ncells + cell]          (canonical pre-collision df(t), FP64)
+ *   density      rho[cell]   (water height h for the shallow-water equilibrium)
+ *   velocity     u[d * ncells + cell], d = 0 (x), 1 (y), 2 (z); D2Q9 ignores/zeroes d = 2
+ * Host or device pointers are accepted wherever a field pointer is taken (detected with
+ * hipPointerGetAttributes).  Pointers are borrowed for the duration of the call only.
+ *
+ * Time convention: df(0) = f^eq(rho0, u0) - f0; lbm_step(1) collides, then streams, so that
+ * after t steps the readers (macroscopic, get_populations, diagnostics) report df(t).
+ *
+ * Errors: every call returns an lbm_status; the message of the last failure of the calling
+ * thread is returned by lbm_last_error().  No call aborts the process.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* invalid argument: enum out of range, dims < 1, n_omegas != q, ...  */
+  LBM_EUNSUPPORTED = -2,  /* inadmissible combination (sec. 3) or not implemented               */
+  LBM_ENOMEM = -3,        /* device allocation failed or caller buffer too small               */
+  LBM_EDEVICE = -4,       /* a HIP runtime error; lbm_last_error() holds the HIP message       */
+  LBM_ENONFINITE = -5     /* lbm_diagnostics found NaN or Inf populations                      */
+} lbm_status;
+
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_stencil;
+typedef enum { LBM_SPACE_RAW = 0, LBM_SPACE_CENTRAL = 1, LBM_SPACE_CUMULANT = 2 } lbm_space;
+typedef enum { LBM_EQ_MAXWELLIAN = 0, LBM_EQ_SHALLOW_WATER = 1 } lbm_equilibrium;
+/* DEFAULT resolves to DELTA for raw and central moments with the Maxwellian, to ABSOLUTE for
+ * cumulants and for the shallow-water equilibrium. */
+typedef enum { LBM_EQFORM_DEFAULT = 0, LBM_EQFORM_ABSOLUTE = 1, LBM_EQFORM_DELTA = 2 } lbm_eq_form;
+/* Storage precision of the populations.  Compute precision is FP64 for F64 storage and FP32
+ * for F32 and F16 storage.  Initialisation and every reader compute in FP64. */
+typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_storage;
+/* PULL: two arrays, each step gathers f_i(x) from x - xi_i.  AA: one array, in place
+ * (even steps read and write the cell's own slots, odd steps read from x - xi_i and write to
+ * x + xi_i); sec. 4.4. */
+typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1 } lbm_streaming;
+
+typedef struct {
+  int stencil;            /* lbm_stencil                                                      */
+  int space;              /* lbm_space                                                        */
+  int equilibrium;        /* lbm_equilibrium                                                  */
+  int eq_form;            /* lbm_eq_form                                                      */
+  int zero_centered;      /* must be 1: populations are stored as df = f - f0 (sec. 2.1)      */
+  const double *omegas;   /* host array of n_omegas rates, basis order above, each in [0, 2]  */
+  int n_omegas;           /* == q                                                             */
+  double gravity;         /* g > 0 for LBM_EQ_SHALLOW_WATER, ignored otherwise                */
+  int64_t nx, ny, nz;     /* lattice size; nz == 1 for D2Q9                                   */
+  int periodic[3];        /* must be {1, 1, 1}                                                */
+  int storage;            /* lbm_storage                                                      */
+  int streaming;          /* lbm_streaming                                                    */
+  void *buffers[2];       /* optional caller-owned device buffers (e.g. torch allocations);   */
+  size_t buffer_bytes;    /* each >= lbm_required_bytes / nbuffers; NULL -> library allocates */
+  void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fill *p with defaults: D3Q27, cumulant, Maxwellian, DEFAULT form, zero-centred, FP32, pull,
+ * periodic, 1x1x1, no rates.  Always succeeds for non-NULL p. */
+lbm_status lbm_params_default(lbm_params *p);
+
+/* Validate a parameter set without touching any device (pure host code).
+ * LBM_EINVAL for bad enums, dims < 1, n_omegas != q, NULL omegas, non-finite or out-of-range
+ * rates, gravity <= 0 with the shallow-water equilibrium.  LBM_EUNSUPPORTED for the
+ * restrictions of sec. 3 (delta-equilibrium needs zero-centred storage; the cumulant space
+ * admits no delta-equilibrium), absolute storage, D2Q9 with nz != 1, the shallow-water
+ * equilibrium on a 3-D stencil or in cumulant space, non-periodic axes. */
+lbm_status lbm_validate(const lbm_params *p);
+
+/* Bytes of device population storage the parameter set needs in total (both arrays for
+ * pull, one for AA): nbuffers * q * ncells * sizeof(storage).  Pure host code. */
+lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes);
+
+/* Create a context: validate, derive the relaxation matrix in monomial form, allocate or
+ * attach device buffers, pick the launch shape.  *out is NULL on failure. */
+lbm_status lbm_create(const lbm_params *p, lbm_ctx **out);
+void lbm_destroy(lbm_ctx *ctx);
+
+/* Initialise df(0) = f^eq(rho, u) - f0 from FP64 fields (sec. 2.4); resets the step counter.
+ * rho: ncells values; u: 3 * ncells values (d = 2 ignored for D2Q9).  Asynchronous on the
+ * context stream when both pointers are device pointers, synchronous otherwise. */
+lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *u);
+
+/* Advance n >= 0 time steps (fused collide + stream).  Asynchronous on the context stream.
+ * With graphs enabled (default) the n launches are recorded once into a hipGraph per
+ * (n, buffer parity) and replayed. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Density (or h) and velocity of df(t), FP64, synchronous. */
+lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho, double *u);
+
+/* Canonical df(t) in natural layout, FP64 (export / import for checks and checkpoints).
+ * set_populations narrows to the storage precision and keeps the step counter. */
+lbm_status lbm_get_populations(lbm_ctx *ctx, double *df);
+lbm_status lbm_set_populations(lbm_ctx *ctx, const double *df);
+
+/* FP64 reductions over df(t): out = {sum drho, sum jx, sum jy, sum jz,
+ * sum rho |u|^2 / 2, number of non-finite populations}.  Deterministic (fixed-order tree).
+ * Returns LBM_ENONFINITE when out[5] > 0 (out is still filled).  Synchronous. */
+lbm_status lbm_diagnostics(lbm_ctx *ctx, double out[6]);
+
+/* Wait for all work queued on the context stream. */
+lbm_status lbm_synchronize(lbm_ctx *ctx);
+
+/* Steps taken since the last init (or as set by lbm_set_time). */
+int64_t lbm_time(const lbm_ctx *ctx);
+/* Set the step counter (checkpoint restore: set_populations, then set_time). */
+lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
+
+/* Launch shape of the sweep: block of bx * by threads covering bx cells along x and by rows
+ * along y; xcd_swizzle != 0 maps consecutive tiles to the same XCD.  bx * by must be a
+ * multiple of 64 and <= 1024. */
+lbm_status lbm_set_launch(lbm_ctx *ctx, int bx, int by, int xcd_swizzle);
+lbm_status lbm_get_launch(const lbm_ctx *ctx, int *bx, int *by, int *xcd_swizzle);
+
+/* Time candidate launch shapes on the context's own buffers (state is left unchanged) and
+ * keep the fastest; results are cached per (method, precision, pattern, size) in the JSON
+ * file named by LBM_AUTOTUNE_CACHE, if set. */
+lbm_status lbm_autotune(lbm_ctx *ctx);
+
+/* Enable (1) or disable (0) hipGraph recording in lbm_step. */
+lbm_status lbm_set_graphs(lbm_ctx *ctx, int enable);
+
+/* Device pointer of population buffer k (0 or 1) and the buffer holding the state that the
+ * next sweep reads; for measurement and checks. */
+lbm_status lbm_buffer(const lbm_ctx *ctx, int k, void **ptr, size_t *bytes);
+
+/* Time n sweeps with HIP events recorded on the context stream; *ms = elapsed milliseconds. */
+lbm_status lbm_time_steps(lbm_ctx *ctx, int64_t n, double *ms);
+
+/* Message of the calling thread's last failure ("" if none). */
+const char *lbm_last_error(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+/* --------------------------------------------------------------------------------------
+ * Batched ensemble: many independent periodic boxes of one method family, each with its
+ * own size and relaxation rates, advanced by one launch per time step over a tile list of
+ * all boxes.  Boxes are stored back to back (box b starts at cell offset sum_{c<b} ncells_c).
+ * Field arguments are the per-box fields concatenated in box order.
+ * -------------------------------------------------------------------------------------- */
+typedef struct lbm_batch lbm_batch;
+
+/* common: stencil, space, equilibrium, eq_form, storage, streaming (pull only), stream;
+ * its dims, omegas and buffers are ignored.  dims: nboxes * 3 (nx, ny, nz);
+ * omegas: nboxes * q rates.  3-D stencils only. */
+lbm_status lbm_batch_create(const lbm_params *common, int nboxes, const int64_t *dims,
+                            const double *omegas, lbm_batch **out);
+void lbm_batch_destroy(lbm_batch *b);
+lbm_status lbm_batch_init_equilibrium(lbm_batch *b, const double *rho, const double *u);
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u);
+lbm_status lbm_batch_get_populations(lbm_batch *b, double *df);
+lbm_status lbm_batch_synchronize(lbm_batch *b);
+int64_t lbm_batch_cells(const lbm_batch *b);
+lbm_status lbm_batch_set_graphs(lbm_batch *b, int enable);
+lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms);
+
+/* --------------------------------------------------------------------------------------
+ * Measurement helpers
+ * -------------------------------------------------------------------------------------- */
+/* Plain device copy of `bytes` bytes (16-byte vector loads and stores) repeated `reps` times,
+ * timed with HIP events; the practical HBM ceiling beside the sweep. */
+lbm_status lbm_copy_bandwidth(void *dst, const void *src, size_t bytes, int reps, void *stream,
+                              double *ms);
+
+/* Test hook: streaming only (the collision replaced by the identity), for checking the
+ * integer index maps of the pull and AA patterns bit for bit. */
+lbm_status lbm_debug_stream_only(lbm_ctx *ctx, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

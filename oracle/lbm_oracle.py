@@ -500,11 +500,15 @@ def macroscopic(method, df):
 
 
 def diagnostics(method, df):
-    """[sum drho, sum jx, sum jy, sum jz, sum rho |u|^2 / 2, #non-finite] over the box."""
-    rho, u = macroscopic(method, df)
-    j = rho[None] * u
-    ke = 0.5 * (rho * (u * u).sum(axis=0)).sum()
-    return np.array([(rho - 1.0).sum(), j[0].sum(), j[1].sum(), j[2].sum(), ke,
+    """[sum drho, sum jx, sum jy, sum jz, sum rho |u|^2 / 2, #non-finite] over the box, with
+    drho = sum_i df_i and j = sum_i df_i xi_i summed directly (eq.
+    DensityAndVelocityFromDeviation), so no background value is subtracted."""
+    st = method.st
+    cells = df.reshape(st.q, -1).T
+    drho = cells.sum(axis=1)
+    j = cells @ st.xi.astype(np.float64)
+    ke = 0.5 * ((j * j).sum(axis=1) / (1.0 + drho)).sum()
+    return np.array([drho.sum(), j[:, 0].sum(), j[:, 1].sum(), j[:, 2].sum(), ke,
                      float((~np.isfinite(df)).sum())])
 
 

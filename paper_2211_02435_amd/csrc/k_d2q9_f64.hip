@@ -1,0 +1,4 @@
+// Kernels of stencil d2q9 with f64 population storage.
+#define LBM_TU_STENCIL 0
+#define LBM_TU_STORE 0
+#include "lbm_instantiate.inc"

@@ -1,0 +1,26 @@
+// Kernel lookup: each translation unit instantiates the kernels of one (stencil, storage)
+// pair and exports them through these tables; the host library launches by pointer.
+#pragma once
+
+namespace lbm {
+
+template <int S, int STORE>
+struct KTable {
+  static const void *sweep(int sp, int eq, int reg, int pat);
+  static const void *init(int sp, int eq, int gm);
+  static const void *exporter(int gm);
+  static const void *importer(int gm);
+  static const void *macro(int gm);
+  static const void *diag(int gm);
+};
+
+const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat);
+const void *init_fn(int s, int store, int sp, int eq, int gm);
+const void *export_fn(int s, int store, int gm);
+const void *import_fn(int s, int store, int gm);
+const void *macro_fn(int s, int store, int gm);
+const void *diag_fn(int s, int store, int gm);
+const void *diag_final_fn();
+const void *copy_fn();
+
+}  // namespace lbm

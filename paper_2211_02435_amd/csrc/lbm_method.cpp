@@ -1,0 +1,271 @@
+// Host-only part of the library: parameter validation and the relaxation matrix.
+//
+// Pure host code (no HIP runtime calls), so the CPU test suite can exercise it without a GPU.
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_method.hpp"
+
+namespace lbm {
+
+thread_local std::string g_last_error;
+
+lbm_status fail(lbm_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+
+int stencil_q(int s) { return s == LBM_D2Q9 ? 9 : (s == LBM_D3Q19 ? 19 : 27); }
+int stencil_d(int s) { return s == LBM_D2Q9 ? 2 : 3; }
+size_t storage_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
+
+int resolve_eq_form(const lbm_params *p) {
+  if (p->eq_form != LBM_EQFORM_DEFAULT) return p->eq_form;
+  if (p->space == LBM_SPACE_CUMULANT || p->equilibrium == LBM_EQ_SHALLOW_WATER) return LBM_EQFORM_ABSOLUTE;
+  return LBM_EQFORM_DELTA;
+}
+
+// ---------------------------------------------------------------------------------------
+// polynomial bases (documented in lbm.h): each polynomial is a list of (coef, a, b, c)
+// ---------------------------------------------------------------------------------------
+struct Term {
+  double c;
+  int a, b, z;
+};
+using Poly = std::vector<Term>;
+
+static std::vector<Poly> basis_of(int s) {
+  std::vector<Poly> B;
+  if (s == LBM_D2Q9) {
+    B = {{{1, 0, 0, 0}}, {{1, 1, 0, 0}}, {{1, 0, 1, 0}}, {{1, 1, 1, 0}},
+         {{1, 2, 0, 0}, {-1, 0, 2, 0}}, {{1, 2, 0, 0}, {1, 0, 2, 0}},
+         {{1, 1, 2, 0}}, {{1, 2, 1, 0}}, {{1, 2, 2, 0}}};
+    return B;
+  }
+  B = {{{1, 0, 0, 0}}, {{1, 1, 0, 0}}, {{1, 0, 1, 0}}, {{1, 0, 0, 1}},
+       {{1, 1, 1, 0}}, {{1, 1, 0, 1}}, {{1, 0, 1, 1}},
+       {{1, 2, 0, 0}, {-1, 0, 2, 0}}, {{1, 2, 0, 0}, {-1, 0, 0, 2}},
+       {{1, 2, 0, 0}, {1, 0, 2, 0}, {1, 0, 0, 2}},
+       {{1, 1, 2, 0}, {1, 1, 0, 2}}, {{1, 1, 2, 0}, {-1, 1, 0, 2}},
+       {{1, 2, 1, 0}, {1, 0, 1, 2}}, {{1, 2, 1, 0}, {-1, 0, 1, 2}},
+       {{1, 2, 0, 1}, {1, 0, 2, 1}}, {{1, 2, 0, 1}, {-1, 0, 2, 1}}};
+  if (s == LBM_D3Q27) B.push_back({{1, 1, 1, 1}});
+  B.push_back({{1, 2, 2, 0}, {-2, 2, 0, 2}, {1, 0, 2, 2}});
+  B.push_back({{1, 2, 2, 0}, {1, 2, 0, 2}, {-2, 0, 2, 2}});
+  B.push_back({{1, 2, 2, 0}, {1, 2, 0, 2}, {1, 0, 2, 2}});
+  if (s == LBM_D3Q27) {
+    B.push_back({{1, 2, 1, 1}});
+    B.push_back({{1, 1, 2, 1}});
+    B.push_back({{1, 1, 1, 2}});
+    B.push_back({{1, 1, 2, 2}});
+    B.push_back({{1, 2, 1, 2}});
+    B.push_back({{1, 2, 2, 1}});
+    B.push_back({{1, 2, 2, 2}});
+  }
+  return B;
+}
+
+static bool mono_present(int s, int e) {
+  const int a = e % 3, b = (e / 3) % 3, c = e / 9;
+  if (s == LBM_D2Q9) return c == 0;
+  if (s == LBM_D3Q19) return a == 0 || b == 0 || c == 0;
+  return true;
+}
+
+// Gauss-Jordan inverse with partial pivoting (n <= 27)
+static bool invert(std::vector<double> &A, int n) {
+  std::vector<double> I(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i) I[size_t(i) * n + i] = 1.0;
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < n; ++r)
+      if (std::fabs(A[size_t(r) * n + c]) > std::fabs(A[size_t(piv) * n + c])) piv = r;
+    if (std::fabs(A[size_t(piv) * n + c]) < 1e-12) return false;
+    if (piv != c)
+      for (int k = 0; k < n; ++k) {
+        std::swap(A[size_t(c) * n + k], A[size_t(piv) * n + k]);
+        std::swap(I[size_t(c) * n + k], I[size_t(piv) * n + k]);
+      }
+    const double d = A[size_t(c) * n + c];
+    for (int k = 0; k < n; ++k) {
+      A[size_t(c) * n + k] /= d;
+      I[size_t(c) * n + k] /= d;
+    }
+    for (int r = 0; r < n; ++r) {
+      if (r == c) continue;
+      const double f = A[size_t(r) * n + c];
+      if (f == 0.0) continue;
+      for (int k = 0; k < n; ++k) {
+        A[size_t(r) * n + k] -= f * A[size_t(c) * n + k];
+        I[size_t(r) * n + k] -= f * I[size_t(c) * n + k];
+      }
+    }
+  }
+  A.swap(I);
+  return true;
+}
+
+static const int kO2_3[6] = {2, 6, 18, 4, 10, 12};
+static const int kO3_3[7] = {7, 19, 5, 21, 11, 15, 13};
+static const int kO4_3[6] = {8, 20, 24, 14, 16, 22};
+static const int kO5_3[3] = {25, 23, 17};
+static const int kO2_2[3] = {2, 6, 4};
+static const int kO3_2[2] = {7, 5};
+
+lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
+  const int q = stencil_q(s), d = stencil_d(s);
+  const std::vector<Poly> B = basis_of(s);
+  if (int(B.size()) != q) return fail(LBM_EINVAL, "internal: basis size mismatch");
+  // monomial columns: present grid indices in increasing order
+  std::vector<int> cols;
+  int colof[27];
+  for (int e = 0; e < 27; ++e) {
+    colof[e] = -1;
+    if (mono_present(s, e)) {
+      colof[e] = int(cols.size());
+      cols.push_back(e);
+    }
+  }
+  if (int(cols.size()) != q) return fail(LBM_EINVAL, "internal: monomial count mismatch");
+  std::vector<double> P(size_t(q) * q, 0.0);
+  for (int r = 0; r < q; ++r)
+    for (const Term &t : B[r]) P[size_t(r) * q + colof[t.a + 3 * t.b + 9 * t.z]] += t.c;
+  std::vector<double> Pinv = P;
+  if (!invert(Pinv, q)) return fail(LBM_EINVAL, "internal: singular basis");
+  // A = P^-1 S P with the conserved rows (1, x, y, z) at rate 0
+  std::vector<double> SP(size_t(q) * q);
+  for (int r = 0; r < q; ++r) {
+    const double w = (r <= d) ? 0.0 : omegas[r];
+    for (int k = 0; k < q; ++k) SP[size_t(r) * q + k] = w * P[size_t(r) * q + k];
+  }
+  std::vector<double> A(size_t(q) * q, 0.0);
+  for (int i = 0; i < q; ++i)
+    for (int k = 0; k < q; ++k) {
+      double acc = 0.0;
+      for (int r = 0; r < q; ++r) acc += Pinv[size_t(i) * q + r] * SP[size_t(r) * q + k];
+      A[size_t(i) * q + k] = acc;
+    }
+  auto ord = [&](int e) { return e % 3 + (e / 3) % 3 + e / 9; };
+  for (int i = 0; i < q; ++i)
+    for (int k = 0; k < q; ++k)
+      if (ord(cols[i]) != ord(cols[k]) && std::fabs(A[size_t(i) * q + k]) > 1e-13)
+        return fail(LBM_EINVAL, "internal: relaxation matrix mixes orders");
+  auto bval = [&](int ei, int ek) -> double {
+    if (colof[ei] < 0 || colof[ek] < 0) return 0.0;
+    const double a = A[size_t(colof[ei]) * q + colof[ek]];
+    return (ei == ek ? 1.0 : 0.0) - a;
+  };
+  std::memset(out, 0, sizeof(*out));
+  if (d == 3) {
+    for (int j = 0; j < 6; ++j)
+      for (int k = 0; k < 6; ++k) out->b2[j][k] = bval(kO2_3[j], kO2_3[k]);
+    for (int j = 0; j < 7; ++j)
+      for (int k = 0; k < 7; ++k) out->b3[j][k] = bval(kO3_3[j], kO3_3[k]);
+    for (int j = 0; j < 6; ++j)
+      for (int k = 0; k < 6; ++k) out->b4[j][k] = bval(kO4_3[j], kO4_3[k]);
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) out->b5[j][k] = bval(kO5_3[j], kO5_3[k]);
+    out->b6 = bval(26, 26);
+  } else {
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) out->b2[j][k] = bval(kO2_2[j], kO2_2[k]);
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k) out->b3[j][k] = bval(kO3_2[j], kO3_2[k]);
+    out->b4[0][0] = bval(8, 8);
+  }
+  // regularized: every block of order >= 3 is zero (all those rates equal 1)
+  double hi = 0.0;
+  for (int i = 0; i < q; ++i)
+    for (int k = 0; k < q; ++k)
+      if (ord(cols[i]) >= 3) hi = std::fmax(hi, std::fabs(bval(cols[i], cols[k])));
+  out->regularized = hi < 1e-14;
+  return LBM_OK;
+}
+
+lbm_status validate(const lbm_params *p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->stencil < LBM_D2Q9 || p->stencil > LBM_D3Q27) return fail(LBM_EINVAL, "stencil out of range");
+  if (p->space < LBM_SPACE_RAW || p->space > LBM_SPACE_CUMULANT) return fail(LBM_EINVAL, "space out of range");
+  if (p->equilibrium < LBM_EQ_MAXWELLIAN || p->equilibrium > LBM_EQ_SHALLOW_WATER)
+    return fail(LBM_EINVAL, "equilibrium out of range");
+  if (p->eq_form < LBM_EQFORM_DEFAULT || p->eq_form > LBM_EQFORM_DELTA) return fail(LBM_EINVAL, "eq_form out of range");
+  if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return fail(LBM_EINVAL, "storage out of range");
+  if (p->streaming < LBM_STREAM_PULL || p->streaming > LBM_STREAM_AA) return fail(LBM_EINVAL, "streaming out of range");
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "dims must be >= 1");
+  const int q = stencil_q(p->stencil);
+  if (!p->omegas) return fail(LBM_EINVAL, "omegas is NULL");
+  if (p->n_omegas != q) return fail(LBM_EINVAL, "n_omegas must equal q = " + std::to_string(q));
+  for (int i = 0; i < q; ++i) {
+    const double w = p->omegas[i];
+    if (!std::isfinite(w)) return fail(LBM_EINVAL, "relaxation rate " + std::to_string(i) + " is not finite");
+    if (i > stencil_d(p->stencil) && (w < 0.0 || w > 2.0))
+      return fail(LBM_EINVAL, "relaxation rate " + std::to_string(i) + " outside [0, 2]");
+  }
+  if (p->equilibrium == LBM_EQ_SHALLOW_WATER && !(p->gravity > 0.0 && std::isfinite(p->gravity)))
+    return fail(LBM_EINVAL, "shallow-water equilibrium needs gravity > 0");
+  // admissibility (sec. 3)
+  if (!p->zero_centered) {
+    if (p->eq_form == LBM_EQFORM_DELTA)
+      return fail(LBM_EUNSUPPORTED, "the delta-equilibrium requires zero-centred storage");
+    return fail(LBM_EUNSUPPORTED, "absolute population storage is not implemented (zero_centered must be 1)");
+  }
+  if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
+    return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");
+  if (p->stencil == LBM_D2Q9 && p->nz != 1) return fail(LBM_EUNSUPPORTED, "D2Q9 requires nz == 1");
+  if (p->equilibrium == LBM_EQ_SHALLOW_WATER) {
+    if (p->stencil != LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the shallow-water equilibrium is two-dimensional (D2Q9)");
+    if (p->space == LBM_SPACE_CUMULANT)
+      return fail(LBM_EUNSUPPORTED, "shallow water in cumulant space is not implemented");
+    if (p->eq_form == LBM_EQFORM_DELTA)
+      return fail(LBM_EUNSUPPORTED, "the shallow-water equilibrium is relaxed in absolute form");
+  }
+  if (!p->periodic[0] || !p->periodic[1] || !p->periodic[2])
+    return fail(LBM_EUNSUPPORTED, "only periodic boundaries are implemented");
+  const double ncells = double(p->nx) * double(p->ny) * double(p->nz);
+  if (ncells * double(storage_bytes(p->storage)) >= 4294967296.0)
+    return fail(LBM_EUNSUPPORTED, "one population plane must stay below 4 GiB (32-bit offsets)");
+  if (p->nx > 2147483647 || p->ny > 2147483647 || p->nz > 2147483647) return fail(LBM_EINVAL, "dims too large");
+  return LBM_OK;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+extern "C" lbm_status lbm_params_default(lbm_params *p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  std::memset(p, 0, sizeof(*p));
+  p->stencil = LBM_D3Q27;
+  p->space = LBM_SPACE_CUMULANT;
+  p->equilibrium = LBM_EQ_MAXWELLIAN;
+  p->eq_form = LBM_EQFORM_DEFAULT;
+  p->zero_centered = 1;
+  p->nx = p->ny = p->nz = 1;
+  p->periodic[0] = p->periodic[1] = p->periodic[2] = 1;
+  p->storage = LBM_STORE_F32;
+  p->streaming = LBM_STREAM_PULL;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_validate(const lbm_params *p) {
+  const lbm_status s = validate(p);
+  if (s != LBM_OK) return s;
+  RelaxHost r;
+  return relaxation_blocks(p->stencil, p->omegas, &r);
+}
+
+extern "C" lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes) {
+  const lbm_status s = validate(p);
+  if (s != LBM_OK) return s;
+  if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
+  const size_t nbuf = p->streaming == LBM_STREAM_PULL ? 2 : 1;
+  *bytes = nbuf * size_t(stencil_q(p->stencil)) * size_t(p->nx) * size_t(p->ny) * size_t(p->nz) *
+           storage_bytes(p->storage);
+  return LBM_OK;
+}
+
+extern "C" const char *lbm_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *lbm_version(void) { return "lbm-mi355x 0.1 (gfx950)"; }

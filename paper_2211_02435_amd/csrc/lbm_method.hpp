@@ -1,0 +1,29 @@
+// Host-side method description shared by the library's translation units.
+#pragma once
+
+#include <string>
+
+#include "../../include/lbm.h"
+
+namespace lbm {
+
+// B = I - P^-1 S P per order (rows/cols in the device's order lists), FP64
+struct RelaxHost {
+  double b2[6][6];
+  double b3[7][7];
+  double b4[6][6];
+  double b5[3][3];
+  double b6;
+  bool regularized;  // every block of order >= 3 vanishes (all those rates equal 1)
+};
+
+extern thread_local std::string g_last_error;
+lbm_status fail(lbm_status s, const std::string &msg);
+int stencil_q(int s);
+int stencil_d(int s);
+size_t storage_bytes(int st);
+int resolve_eq_form(const lbm_params *p);
+lbm_status validate(const lbm_params *p);
+lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out);
+
+}  // namespace lbm

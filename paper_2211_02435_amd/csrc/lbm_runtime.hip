@@ -1,0 +1,1115 @@
+// Runtime of the lattice Boltzmann library: contexts, launches, hipGraph replay of time
+// loops, readers/writers of the canonical state, reductions, launch-shape autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_dispatch.hpp"
+#include "lbm_kernels.hpp"
+#include "lbm_method.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------------------
+// dispatch over the per-(stencil, storage) tables
+// ---------------------------------------------------------------------------------------
+#define LBM_TABLE_CALL(FN, ...)                                                   \
+  switch (s * 3 + store) {                                                        \
+    case 0: return KTable<D2Q9, F64>::FN(__VA_ARGS__);                            \
+    case 1: return KTable<D2Q9, F32>::FN(__VA_ARGS__);                            \
+    case 2: return KTable<D2Q9, F16>::FN(__VA_ARGS__);                            \
+    case 3: return KTable<D3Q19, F64>::FN(__VA_ARGS__);                           \
+    case 4: return KTable<D3Q19, F32>::FN(__VA_ARGS__);                           \
+    case 5: return KTable<D3Q19, F16>::FN(__VA_ARGS__);                           \
+    case 6: return KTable<D3Q27, F64>::FN(__VA_ARGS__);                           \
+    case 7: return KTable<D3Q27, F32>::FN(__VA_ARGS__);                           \
+    case 8: return KTable<D3Q27, F16>::FN(__VA_ARGS__);                           \
+  }                                                                               \
+  return nullptr;
+
+const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweep, sp, eq, reg, pat) }
+const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
+const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
+const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
+const void *macro_fn(int s, int store, int gm) { LBM_TABLE_CALL(macro, gm) }
+const void *diag_fn(int s, int store, int gm) { LBM_TABLE_CALL(diag, gm) }
+
+__global__ void __launch_bounds__(DIAG_THREADS) diag_final_kernel(const double *partials, int nblocks, double *out) {
+  __shared__ double red[6][DIAG_THREADS];
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += DIAG_THREADS)
+    for (int k = 0; k < 6; ++k) acc[k] += partials[size_t(b) * 6 + k];
+  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
+    if (int(threadIdx.x) < s)
+      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// plain 16-byte copy: the practical HBM ceiling
+__global__ void __launch_bounds__(256) copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n) {
+  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) dst[i] = src[i];
+}
+
+const void *diag_final_fn() { return reinterpret_cast<const void *>(&diag_final_kernel); }
+const void *copy_fn() { return reinterpret_cast<const void *>(&copy_kernel); }
+
+static lbm_status hip_fail(hipError_t e, const char *what) {
+  return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPCHECK(call, what)                 \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+static bool is_device_ptr(const void *p) {
+  if (!p) return false;
+  hipPointerAttribute_t a;
+  hipError_t e = hipPointerGetAttributes(&a, p);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+}  // namespace lbm
+
+using namespace lbm;
+
+struct lbm_ctx {
+  lbm_params p;
+  std::vector<double> omegas;
+  int s = 0, q = 0, d = 0, space = 0, eq = 0, store = 0, pattern = 0;
+  int nx = 1, ny = 1, nz = 1;
+  uint32_t ncells = 0;
+  size_t elem = 4;
+  RelaxHost R{};
+  bool reg = false;
+  void *buf[2] = {nullptr, nullptr};
+  bool own[2] = {false, false};
+  int nbuf = 2;
+  size_t plane_bytes = 0, buf_bytes = 0;
+  int cur = 0;        // pull: buffer holding the state
+  int64_t t = 0;      // steps since init
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int bx = 64, by = 4, swz = 0;
+  bool graphs = true;
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
+  double *staging = nullptr;
+  size_t staging_doubles = 0;
+  double *partials = nullptr;
+  int diag_blocks = 0;
+};
+
+namespace lbm {
+
+template <class ST, class CT>
+static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void *dst) {
+  SweepArgs<ST, CT> a;
+  std::memset(&a, 0, sizeof(a));
+  a.src = static_cast<const ST *>(src);
+  a.dst = static_cast<ST *>(dst);
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  a.ncells = c->ncells;
+  a.tiles_x = (c->nx + c->bx - 1) / c->bx;
+  a.tiles_y = (c->ny + c->by - 1) / c->by;
+  a.swizzle = c->swz;
+  a.grav = CT(c->p.gravity);
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) a.R.b2[j][k] = CT(c->R.b2[j][k]);
+  for (int j = 0; j < 7; ++j)
+    for (int k = 0; k < 7; ++k) a.R.b3[j][k] = CT(c->R.b3[j][k]);
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) a.R.b4[j][k] = CT(c->R.b4[j][k]);
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) a.R.b5[j][k] = CT(c->R.b5[j][k]);
+  a.R.b6 = CT(c->R.b6);
+  return a;
+}
+
+static dim3 sweep_grid(const lbm_ctx *c) {
+  const uint64_t tx = (c->nx + c->bx - 1) / c->bx, ty = (c->ny + c->by - 1) / c->by;
+  return dim3(unsigned(tx * ty * uint64_t(c->nz)));
+}
+
+template <class ST, class CT>
+static hipError_t launch_sweep_t(const lbm_ctx *c, const void *fn, const void *src, void *dst) {
+  SweepArgs<ST, CT> a = make_sweep_args<ST, CT>(c, src, dst);
+  void *args[] = {&a};
+  return hipLaunchKernel(fn, sweep_grid(c), dim3(c->bx, c->by), args, 0, c->stream);
+}
+
+static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src, void *dst) {
+  switch (c->store) {
+    case F64: return launch_sweep_t<double, double>(c, fn, src, dst);
+    case F32: return launch_sweep_t<float, float>(c, fn, src, dst);
+    default: return launch_sweep_t<_Float16, float>(c, fn, src, dst);
+  }
+}
+
+// one step with the context's current state; advances cur / t
+static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
+  const int sp = sp_override >= 0 ? sp_override : c->space;
+  const int reg = sp_override >= 0 ? 0 : (c->reg ? 1 : 0);
+  const int eq = sp_override >= 0 ? MAXWELL : c->eq;
+  int pat;
+  const void *src;
+  void *dst;
+  if (c->pattern == LBM_STREAM_PULL) {
+    pat = PULL;
+    src = c->buf[c->cur];
+    dst = c->buf[c->cur ^ 1];
+  } else {
+    pat = (c->t % 2 == 0) ? AA_EVEN : AA_ODD;
+    src = c->buf[0];
+    dst = c->buf[0];
+  }
+  const void *fn = sweep_fn(c->s, c->store, sp, eq, reg, pat);
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
+  HIPCHECK(launch_sweep(c, fn, src, dst), "sweep launch");
+  if (c->pattern == LBM_STREAM_PULL) c->cur ^= 1;
+  c->t += 1;
+  return LBM_OK;
+}
+
+static int state_gather_mode(const lbm_ctx *c) {
+  if (c->pattern == LBM_STREAM_PULL) return G_SHIFTED;
+  return (c->t % 2 == 0) ? G_NATURAL : G_AA_ODD;
+}
+static void *state_buffer(const lbm_ctx *c) { return c->pattern == LBM_STREAM_PULL ? c->buf[c->cur] : c->buf[0]; }
+
+static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
+  FieldArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.buf = buf;
+  a.plane = c->ncells;
+  a.ncells = c->ncells;
+  a.nx = c->nx;
+  a.ny = c->ny;
+  a.nz = c->nz;
+  a.tiles_x = (c->nx + fbx - 1) / fbx;
+  a.tiles_y = (c->ny + fby - 1) / fby;
+  a.grav = c->p.gravity;
+  return a;
+}
+
+static const int FBX = 64, FBY = 4;
+static dim3 field_grid(const FieldArgs &a, int nz) { return dim3(unsigned(uint64_t(a.tiles_x) * a.tiles_y * nz)); }
+
+static lbm_status launch_field(lbm_ctx *c, const void *fn, FieldArgs &a) {
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no kernel for this layout");
+  void *args[] = {&a};
+  HIPCHECK(hipLaunchKernel(fn, field_grid(a, c->nz), dim3(FBX, FBY), args, 0, c->stream), "field kernel launch");
+  return LBM_OK;
+}
+
+static lbm_status ensure_staging(lbm_ctx *c, size_t ndoubles) {
+  if (c->staging_doubles >= ndoubles) return LBM_OK;
+  if (c->staging) {
+    HIPCHECK(hipStreamSynchronize(c->stream), "sync");
+    (void)hipFree(c->staging);
+    c->staging = nullptr;
+    c->staging_doubles = 0;
+  }
+  hipError_t e = hipMalloc(&c->staging, ndoubles * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "staging allocation failed");
+  }
+  c->staging_doubles = ndoubles;
+  return LBM_OK;
+}
+
+static void clear_graphs(lbm_ctx *c) {
+  for (auto &kv : c->gcache) (void)hipGraphExecDestroy(kv.second);
+  c->gcache.clear();
+}
+
+static lbm_status check_ctx(const lbm_ctx *c) {
+  if (!c) return fail(LBM_EINVAL, "context is NULL");
+  return LBM_OK;
+}
+
+}  // namespace lbm
+
+// =======================================================================================
+// C ABI
+// =======================================================================================
+extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  lbm_status s = validate(p);
+  if (s != LBM_OK) return s;
+  lbm_ctx *c = new lbm_ctx();
+  c->p = *p;
+  c->omegas.assign(p->omegas, p->omegas + p->n_omegas);
+  c->p.omegas = c->omegas.data();
+  c->s = p->stencil;
+  c->q = stencil_q(p->stencil);
+  c->d = stencil_d(p->stencil);
+  c->space = p->space;
+  c->eq = p->equilibrium == LBM_EQ_SHALLOW_WATER ? SWE : MAXWELL;
+  c->store = p->storage;
+  c->pattern = p->streaming;
+  c->nx = int(p->nx);
+  c->ny = int(p->ny);
+  c->nz = int(p->nz);
+  c->ncells = uint32_t(p->nx * p->ny * p->nz);
+  c->elem = storage_bytes(p->storage);
+  s = relaxation_blocks(c->s, c->omegas.data(), &c->R);
+  if (s != LBM_OK) {
+    delete c;
+    return s;
+  }
+  c->reg = c->R.regularized;
+  c->nbuf = c->pattern == LBM_STREAM_PULL ? 2 : 1;
+  c->plane_bytes = size_t(c->ncells) * c->elem;
+  c->buf_bytes = c->plane_bytes * size_t(c->q);
+  for (int k = 0; k < c->nbuf; ++k) {
+    if (p->buffers[k]) {
+      if (p->buffer_bytes < c->buf_bytes) {
+        delete c;
+        return fail(LBM_ENOMEM, "caller buffer smaller than q * ncells * sizeof(storage)");
+      }
+      c->buf[k] = p->buffers[k];
+      c->own[k] = false;
+    } else {
+      hipError_t e = hipMalloc(&c->buf[k], c->buf_bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        lbm_destroy(c);
+        return fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,
+                    std::string("population buffer allocation: ") + hipGetErrorString(e));
+      }
+      c->own[k] = true;
+    }
+  }
+  if (p->stream) {
+    c->stream = static_cast<hipStream_t>(p->stream);
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      lbm_destroy(c);
+      return hip_fail(e, "stream creation");
+    }
+    c->own_stream = true;
+  }
+  // default launch shape: 256 threads, as wide along x as the row allows
+  int bx = 64;
+  while (bx < 256 && bx < c->nx) bx *= 2;
+  c->bx = bx;
+  c->by = std::max(1, 256 / bx);
+  c->swz = 0;
+  c->diag_blocks = int(std::min<uint64_t>(2048, (uint64_t(c->ncells) + DIAG_THREADS - 1) / DIAG_THREADS));
+  hipError_t e = hipMalloc(&c->partials, (size_t(c->diag_blocks) * 6 + 8) * sizeof(double));
+  if (e != hipSuccess) {
+    lbm_destroy(c);
+    return hip_fail(e, "partials allocation");
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+extern "C" void lbm_destroy(lbm_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  clear_graphs(c);
+  for (int k = 0; k < 2; ++k)
+    if (c->own[k] && c->buf[k]) (void)hipFree(c->buf[k]);
+  if (c->staging) (void)hipFree(c->staging);
+  if (c->partials) (void)hipFree(c->partials);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const double *u) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!rho || !u) return fail(LBM_EINVAL, "rho and u must be non-NULL");
+  const size_t n = c->ncells;
+  const double *drho = rho, *du = u;
+  bool host = !is_device_ptr(rho) || !is_device_ptr(u);
+  if (host) {
+    lbm_status s = ensure_staging(c, 4 * n);
+    if (s != LBM_OK) return s;
+    HIPCHECK(hipMemcpyAsync(c->staging, rho, n * sizeof(double), hipMemcpyDefault, c->stream), "copy rho");
+    HIPCHECK(hipMemcpyAsync(c->staging + n, u, size_t(c->d) * n * sizeof(double), hipMemcpyDefault, c->stream),
+             "copy u");
+    if (c->d == 2) HIPCHECK(hipMemsetAsync(c->staging + 3 * n, 0, n * sizeof(double), c->stream), "zero u_z");
+    drho = c->staging;
+    du = c->staging + n;
+  }
+  c->t = 0;
+  c->cur = 0;
+  const int gm = c->pattern == LBM_STREAM_PULL ? G_SHIFTED : G_NATURAL;
+  const int sp_init = c->eq == SWE ? CENTRAL : c->space;
+  FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
+  a.rho_in = drho;
+  a.u_in = du;
+  lbm_status s = launch_field(c, init_fn(c->s, c->store, sp_init, c->eq, gm), a);
+  if (s != LBM_OK) return s;
+  if (host) HIPCHECK(hipStreamSynchronize(c->stream), "init sync");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!c->graphs || n < 2) {
+    for (int64_t k = 0; k < n; ++k) {
+      lbm_status s = one_step(c);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  }
+  const int parity = c->pattern == LBM_STREAM_PULL ? c->cur : int(c->t % 2);
+  auto key = std::make_pair(n, parity);
+  auto it = c->gcache.find(key);
+  if (it == c->gcache.end()) {
+    const int cur0 = c->cur;
+    const int64_t t0 = c->t;
+    HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    lbm_status s = LBM_OK;
+    for (int64_t k = 0; k < n && s == LBM_OK; ++k) s = one_step(c);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->cur = cur0;
+    c->t = t0;
+    if (s != LBM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    it = c->gcache.emplace(key, ex).first;
+  }
+  HIPCHECK(hipGraphLaunch(it->second, c->stream), "graph launch");
+  if (c->pattern == LBM_STREAM_PULL) c->cur ^= int(n & 1);
+  c->t += n;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_debug_stream_only(lbm_ctx *c, int64_t n) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  for (int64_t k = 0; k < n; ++k) {
+    lbm_status s = one_step(c, IDENTITY);
+    if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_macroscopic(lbm_ctx *c, double *rho, double *u) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!rho || !u) return fail(LBM_EINVAL, "rho and u must be non-NULL");
+  const size_t n = c->ncells;
+  const bool dev = is_device_ptr(rho) && is_device_ptr(u);
+  double *r = rho, *v = u;
+  if (!dev) {
+    lbm_status s = ensure_staging(c, 4 * n);
+    if (s != LBM_OK) return s;
+    r = c->staging;
+    v = c->staging + n;
+  }
+  FieldArgs a = field_args(c, state_buffer(c), FBX, FBY);
+  a.rho_out = r;
+  a.u_out = v;
+  lbm_status s = launch_field(c, macro_fn(c->s, c->store, state_gather_mode(c)), a);
+  if (s != LBM_OK) return s;
+  if (!dev) {
+    HIPCHECK(hipMemcpyAsync(rho, r, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy rho");
+    HIPCHECK(hipMemcpyAsync(u, v, size_t(c->d) * n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy u");
+  }
+  HIPCHECK(hipStreamSynchronize(c->stream), "macroscopic sync");
+  return LBM_OK;
+}
+
+static lbm_status transfer_populations(lbm_ctx *c, double *df, bool to_host_layout) {
+  const size_t n = c->ncells;
+  const bool dev = is_device_ptr(df);
+  const int gm = state_gather_mode(c);
+  const void *fn = to_host_layout ? export_fn(c->s, c->store, gm) : import_fn(c->s, c->store, gm);
+  if (dev) {
+    FieldArgs a = field_args(c, state_buffer(c), FBX, FBY);
+    a.pop = df;
+    a.i0 = 0;
+    a.i1 = c->q;
+    lbm_status s = launch_field(c, fn, a);
+    if (s != LBM_OK) return s;
+    HIPCHECK(hipStreamSynchronize(c->stream), "population sync");
+    return LBM_OK;
+  }
+  const size_t budget = size_t(256) << 20;  // bytes of staging per chunk
+  int per = int(std::max<size_t>(1, budget / (n * sizeof(double))));
+  per = std::min(per, c->q);
+  lbm_status s = ensure_staging(c, size_t(per) * n);
+  if (s != LBM_OK) return s;
+  for (int i0 = 0; i0 < c->q; i0 += per) {
+    const int i1 = std::min(c->q, i0 + per);
+    const size_t bytes = size_t(i1 - i0) * n * sizeof(double);
+    if (!to_host_layout)
+      HIPCHECK(hipMemcpyAsync(c->staging, df + size_t(i0) * n, bytes, hipMemcpyHostToDevice, c->stream), "copy in");
+    FieldArgs a = field_args(c, state_buffer(c), FBX, FBY);
+    a.pop = c->staging;
+    a.i0 = i0;
+    a.i1 = i1;
+    s = launch_field(c, fn, a);
+    if (s != LBM_OK) return s;
+    if (to_host_layout)
+      HIPCHECK(hipMemcpyAsync(df + size_t(i0) * n, c->staging, bytes, hipMemcpyDeviceToHost, c->stream), "copy out");
+    HIPCHECK(hipStreamSynchronize(c->stream), "population sync");
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_populations(lbm_ctx *c, double *df) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!df) return fail(LBM_EINVAL, "df is NULL");
+  return transfer_populations(c, df, true);
+}
+
+extern "C" lbm_status lbm_set_populations(lbm_ctx *c, const double *df) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!df) return fail(LBM_EINVAL, "df is NULL");
+  return transfer_populations(c, const_cast<double *>(df), false);
+}
+
+extern "C" lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  FieldArgs a = field_args(c, state_buffer(c), FBX, FBY);
+  a.partials = c->partials;
+  const void *fn = diag_fn(c->s, c->store, state_gather_mode(c));
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no diagnostics kernel");
+  void *args[] = {&a};
+  HIPCHECK(hipLaunchKernel(fn, dim3(c->diag_blocks), dim3(DIAG_THREADS), args, 0, c->stream), "diag launch");
+  double *dout = c->partials + size_t(c->diag_blocks) * 6;
+  int nb = c->diag_blocks;
+  void *args2[] = {&c->partials, &nb, &dout};
+  HIPCHECK(hipLaunchKernel(diag_final_fn(), dim3(1), dim3(DIAG_THREADS), args2, 0, c->stream), "diag final launch");
+  HIPCHECK(hipMemcpyAsync(out, dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "diag copy");
+  HIPCHECK(hipStreamSynchronize(c->stream), "diag sync");
+  if (out[5] > 0.0) return fail(LBM_ENONFINITE, "non-finite populations found");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_synchronize(lbm_ctx *c) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  HIPCHECK(hipStreamSynchronize(c->stream), "synchronize");
+  return LBM_OK;
+}
+
+extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
+
+extern "C" lbm_status lbm_set_time(lbm_ctx *c, int64_t t) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
+  if (c->pattern == LBM_STREAM_AA && (t % 2) != (c->t % 2)) {
+    // odd and even times use different layouts: move the state pair by pair (slots i and
+    // opp(i) only exchange with each other) from the old layout to the new one
+    const size_t n = c->ncells;
+    lbm_status s = ensure_staging(c, 2 * n);
+    if (s != LBM_OK) return s;
+    const int gm_old = state_gather_mode(c);
+    const int gm_new = (t % 2 == 0) ? G_NATURAL : G_AA_ODD;
+    for (int i0 = 0; i0 < c->q; i0 = (i0 == 0 ? 1 : i0 + 2)) {
+      FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
+      a.pop = c->staging;
+      a.i0 = i0;
+      a.i1 = i0 == 0 ? 1 : i0 + 2;
+      s = launch_field(c, export_fn(c->s, c->store, gm_old), a);
+      if (s == LBM_OK) s = launch_field(c, import_fn(c->s, c->store, gm_new), a);
+      if (s != LBM_OK) return s;
+    }
+    HIPCHECK(hipStreamSynchronize(c->stream), "relayout sync");
+  }
+  clear_graphs(c);
+  c->t = t;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_launch(lbm_ctx *c, int bx, int by, int swz) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (bx < 1 || by < 1 || (bx * by) % 64 != 0 || bx * by > 512)
+    return fail(LBM_EINVAL, "bx * by must be a positive multiple of 64 and at most 512");
+  if (c->bx != bx || c->by != by || c->swz != (swz ? 1 : 0)) clear_graphs(c);
+  c->bx = bx;
+  c->by = by;
+  c->swz = swz ? 1 : 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_get_launch(const lbm_ctx *c, int *bx, int *by, int *swz) {
+  if (!c || !bx || !by || !swz) return fail(LBM_EINVAL, "NULL argument");
+  *bx = c->bx;
+  *by = c->by;
+  *swz = c->swz;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_graphs(lbm_ctx *c, int enable) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  c->graphs = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_buffer(const lbm_ctx *c, int k, void **ptr, size_t *bytes) {
+  if (!c || !ptr) return fail(LBM_EINVAL, "NULL argument");
+  if (k < 0 || k >= c->nbuf) return fail(LBM_EINVAL, "buffer index out of range");
+  *ptr = c->buf[k];
+  if (bytes) *bytes = c->buf_bytes;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_time_steps(lbm_ctx *c, int64_t n, double *ms) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!ms) return fail(LBM_EINVAL, "ms is NULL");
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  HIPCHECK(hipEventCreate(&e1), "event");
+  HIPCHECK(hipEventRecord(e0, c->stream), "event record");
+  lbm_status s = lbm_step(c, n);
+  HIPCHECK(hipEventRecord(e1, c->stream), "event record");
+  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  float f = 0.f;
+  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = double(f);
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------
+// autotuning of the launch shape
+// ---------------------------------------------------------------------------------------
+static std::string tune_key(const lbm_ctx *c) {
+  std::ostringstream k;
+  k << "s" << c->s << "_sp" << c->space << "_eq" << c->eq << "_r" << int(c->reg) << "_st" << c->store << "_pat"
+    << c->pattern << "_" << c->nx << "x" << c->ny << "x" << c->nz;
+  return k.str();
+}
+
+static bool cache_lookup(const std::string &file, const std::string &key, int *bx, int *by, int *swz) {
+  std::ifstream in(file);
+  if (!in) return false;
+  std::string line;
+  const std::string pat = "\"" + key + "\"";
+  while (std::getline(in, line)) {
+    size_t p = line.find(pat);
+    if (p == std::string::npos) continue;
+    size_t lb = line.find('[', p);
+    if (lb == std::string::npos) continue;
+    double ms = 0;
+    if (std::sscanf(line.c_str() + lb, "[%d, %d, %d, %lf", bx, by, swz, &ms) >= 3) return true;
+  }
+  return false;
+}
+
+static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, double ms) {
+  std::vector<std::string> lines;
+  {
+    std::ifstream in(file);
+    std::string line;
+    while (std::getline(in, line)) {
+      if (line.find('"') == std::string::npos) continue;
+      if (line.find("\"" + key + "\"") != std::string::npos) continue;
+      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
+      lines.push_back(line);
+    }
+  }
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %.6f]", key.c_str(), bx, by, swz, ms);
+  lines.push_back(buf);
+  std::ofstream out(file, std::ios::trunc);
+  out << "{\n";
+  for (size_t i = 0; i < lines.size(); ++i) out << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  out << "}\n";
+}
+
+extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  const char *file = std::getenv("LBM_AUTOTUNE_CACHE");
+  const std::string key = tune_key(c);
+  int bx, by, swz;
+  if (file && cache_lookup(file, key, &bx, &by, &swz)) return lbm_set_launch(c, bx, by, swz);
+  // candidate shapes
+  std::vector<std::array<int, 3>> cand;
+  for (int cbx : {64, 128, 256, 512})
+    for (int cby : {1, 2, 4, 8})
+      for (int cs : {0, 1}) {
+        if (cbx * cby > 512 || (cbx * cby) % 64 != 0) continue;
+        if (cbx > 64 && cbx / 2 >= c->nx) continue;
+        if (cby > 1 && cby / 2 >= c->ny) continue;
+        cand.push_back({cbx, cby, cs});
+      }
+  // the sweep must leave the state unchanged: pull writes only the other buffer; AA runs
+  // on a copy of the buffer that is restored afterwards
+  void *saved = nullptr;
+  if (c->pattern == LBM_STREAM_AA) {
+    hipError_t e = hipMalloc(&saved, c->buf_bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBM_ENOMEM, "autotuning the in-place pattern needs a temporary copy of the state");
+    }
+    HIPCHECK(hipMemcpyAsync(saved, c->buf[0], c->buf_bytes, hipMemcpyDeviceToDevice, c->stream), "save state");
+  }
+  const int cur0 = c->cur;
+  const int64_t t0 = c->t;
+  const int bx0 = c->bx, by0 = c->by, swz0 = c->swz;
+  const bool g0 = c->graphs;
+  c->graphs = false;
+  const uint64_t lups = uint64_t(c->ncells);
+  const int reps = int(std::max<uint64_t>(2, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
+  double best = 1e300;
+  int bb[3] = {bx0, by0, swz0};
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  HIPCHECK(hipEventCreate(&e1), "event");
+  lbm_status st = LBM_OK;
+  for (const auto &cd : cand) {
+    c->bx = cd[0];
+    c->by = cd[1];
+    c->swz = cd[2];
+    // warm-up, then time reps sweeps; pull: same src -> dst every time
+    for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
+      if (r == 1) (void)hipEventRecord(e0, c->stream);
+      c->cur = cur0;
+      c->t = t0;
+      st = one_step(c);
+    }
+    (void)hipEventRecord(e1, c->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (st != LBM_OK) break;
+    if (ms < best) {
+      best = ms;
+      bb[0] = cd[0];
+      bb[1] = cd[1];
+      bb[2] = cd[2];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->cur = cur0;
+  c->t = t0;
+  c->graphs = g0;
+  if (saved) {
+    (void)hipMemcpyAsync(c->buf[0], saved, c->buf_bytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(saved);
+  }
+  if (st != LBM_OK) return st;
+  c->bx = bx0;
+  c->by = by0;
+  c->swz = swz0;
+  lbm_status s2 = lbm_set_launch(c, bb[0], bb[1], bb[2]);
+  if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], best / reps);
+  return s2;
+}
+
+extern "C" lbm_status lbm_copy_bandwidth(void *dst, const void *src, size_t bytes, int reps, void *stream, double *ms) {
+  if (!dst || !src || !ms || reps < 1) return fail(LBM_EINVAL, "bad argument");
+  if (bytes % 16 != 0) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t n = bytes / 16;
+  const unsigned blocks = unsigned(std::min<size_t>(65536, (n + 255) / 256));
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  HIPCHECK(hipEventCreate(&e1), "event");
+  uint4 *d = static_cast<uint4 *>(dst);
+  const uint4 *sp = static_cast<const uint4 *>(src);
+  void *args[] = {&d, &sp, const_cast<size_t *>(&n)};
+  HIPCHECK(hipLaunchKernel(copy_fn(), dim3(blocks), dim3(256), args, 0, s), "copy launch");
+  HIPCHECK(hipEventRecord(e0, s), "event record");
+  for (int r = 0; r < reps; ++r)
+    HIPCHECK(hipLaunchKernel(copy_fn(), dim3(blocks), dim3(256), args, 0, s), "copy launch");
+  HIPCHECK(hipEventRecord(e1, s), "event record");
+  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  float f = 0.f;
+  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = double(f);
+  return LBM_OK;
+}
+
+// =======================================================================================
+// batched ensemble
+// =======================================================================================
+#include "lbm_batch_kernels.hpp"
+
+namespace lbm {
+const void *batch_sweep_fn(int s, int store, int sp, int reg) {
+  switch (s * 3 + store) {
+    case 3: return BTable<D3Q19, F64>::sweep(sp, reg);
+    case 4: return BTable<D3Q19, F32>::sweep(sp, reg);
+    case 5: return BTable<D3Q19, F16>::sweep(sp, reg);
+    case 6: return BTable<D3Q27, F64>::sweep(sp, reg);
+    case 7: return BTable<D3Q27, F32>::sweep(sp, reg);
+    case 8: return BTable<D3Q27, F16>::sweep(sp, reg);
+  }
+  return nullptr;
+}
+}  // namespace lbm
+
+struct lbm_batch {
+  lbm_params p;
+  int s = 0, q = 0, d = 0, space = 0, store = 0;
+  bool reg = true;
+  size_t elem = 4;
+  int nboxes = 0;
+  std::vector<BoxInfo> boxes;
+  uint32_t ntot = 0, ntiles = 0;
+  BoxInfo *boxes_d = nullptr;
+  uint32_t *tile_box_d = nullptr;
+  void *relax_d = nullptr;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  int64_t t = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  bool graphs = true;
+  std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
+  double *staging = nullptr;
+  size_t staging_doubles = 0;
+};
+
+namespace lbm {
+
+static lbm_status batch_one_step(lbm_batch *b) {
+  const void *fn = batch_sweep_fn(b->s, b->store, b->space, b->reg ? 1 : 0);
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no batched sweep kernel for this method");
+  hipError_t e;
+  auto go = [&](auto tag) {
+    using ST = typename decltype(tag)::first_type;
+    using CT = typename decltype(tag)::second_type;
+    BatchArgs<ST, CT> a;
+    a.src = static_cast<const ST *>(b->buf[b->cur]);
+    a.dst = static_cast<ST *>(b->buf[b->cur ^ 1]);
+    a.ntot = b->ntot;
+    a.boxes = b->boxes_d;
+    a.tile_box = b->tile_box_d;
+    a.relax = static_cast<const Relax<CT> *>(b->relax_d);
+    void *args[] = {&a};
+    return hipLaunchKernel(fn, dim3(b->ntiles), dim3(BATCH_THREADS), args, 0, b->stream);
+  };
+  if (b->store == F64) e = go(std::pair<double, double>());
+  else if (b->store == F32) e = go(std::pair<float, float>());
+  else e = go(std::pair<_Float16, float>());
+  HIPCHECK(e, "batched sweep launch");
+  b->cur ^= 1;
+  b->t += 1;
+  return LBM_OK;
+}
+
+static lbm_status batch_staging(lbm_batch *b, size_t nd) {
+  if (b->staging_doubles >= nd) return LBM_OK;
+  if (b->staging) {
+    HIPCHECK(hipStreamSynchronize(b->stream), "sync");
+    (void)hipFree(b->staging);
+    b->staging = nullptr;
+    b->staging_doubles = 0;
+  }
+  hipError_t e = hipMalloc(&b->staging, nd * sizeof(double));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(LBM_ENOMEM, "staging allocation failed");
+  }
+  b->staging_doubles = nd;
+  return LBM_OK;
+}
+
+static FieldArgs batch_field(const lbm_batch *b, int k, void *base) {
+  const BoxInfo &B = b->boxes[k];
+  FieldArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.buf = static_cast<char *>(base) + size_t(B.off) * b->elem;
+  a.plane = b->ntot;
+  a.ncells = B.ncells;
+  a.nx = B.nx;
+  a.ny = B.ny;
+  a.nz = B.nz;
+  a.tiles_x = (B.nx + FBX - 1) / FBX;
+  a.tiles_y = (B.ny + FBY - 1) / FBY;
+  return a;
+}
+
+static lbm_status batch_launch_field(lbm_batch *b, const void *fn, FieldArgs &a) {
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no kernel for this layout");
+  void *args[] = {&a};
+  HIPCHECK(hipLaunchKernel(fn, field_grid(a, a.nz), dim3(FBX, FBY), args, 0, b->stream), "field kernel launch");
+  return LBM_OK;
+}
+
+}  // namespace lbm
+
+extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, const int64_t *dims,
+                                       const double *omegas, lbm_batch **out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!common || !dims || !omegas || nboxes < 1) return fail(LBM_EINVAL, "bad batch arguments");
+  if (common->stencil == LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the batched ensemble is three-dimensional");
+  if (common->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the pull pattern");
+  if (common->equilibrium != LBM_EQ_MAXWELLIAN) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the Maxwellian");
+  lbm_batch *b = new lbm_batch();
+  b->p = *common;
+  b->s = common->stencil;
+  b->q = stencil_q(b->s);
+  b->d = 3;
+  b->space = common->space;
+  b->store = common->storage;
+  b->elem = storage_bytes(b->store);
+  b->nboxes = nboxes;
+  std::vector<RelaxHost> rh(nboxes);
+  uint64_t off = 0, tiles = 0;
+  for (int k = 0; k < nboxes; ++k) {
+    lbm_params pk = *common;
+    pk.nx = dims[3 * k];
+    pk.ny = dims[3 * k + 1];
+    pk.nz = dims[3 * k + 2];
+    pk.omegas = omegas + size_t(k) * b->q;
+    pk.n_omegas = b->q;
+    lbm_status s = validate(&pk);
+    if (s == LBM_OK) s = relaxation_blocks(b->s, pk.omegas, &rh[k]);
+    if (s != LBM_OK) {
+      delete b;
+      return fail(s, "box " + std::to_string(k) + ": " + g_last_error);
+    }
+    b->reg = b->reg && rh[k].regularized;
+    BoxInfo B;
+    B.off = uint32_t(off);
+    B.ncells = uint32_t(pk.nx * pk.ny * pk.nz);
+    B.tile0 = uint32_t(tiles);
+    B.nx = int(pk.nx);
+    B.ny = int(pk.ny);
+    B.nz = int(pk.nz);
+    b->boxes.push_back(B);
+    off += B.ncells;
+    tiles += (B.ncells + BATCH_THREADS - 1) / BATCH_THREADS;
+  }
+  if (off * b->elem >= (uint64_t(1) << 32) || tiles >= (uint64_t(1) << 31)) {
+    delete b;
+    return fail(LBM_EUNSUPPORTED, "one population plane of the ensemble must stay below 4 GiB");
+  }
+  b->ntot = uint32_t(off);
+  b->ntiles = uint32_t(tiles);
+  std::vector<uint32_t> tb(b->ntiles);
+  for (int k = 0; k < nboxes; ++k) {
+    const uint32_t nt = (b->boxes[k].ncells + BATCH_THREADS - 1) / BATCH_THREADS;
+    for (uint32_t j = 0; j < nt; ++j) tb[b->boxes[k].tile0 + j] = uint32_t(k);
+  }
+  auto bail = [&](hipError_t e, const char *what) {
+    lbm_batch_destroy(b);
+    return hip_fail(e, what);
+  };
+  hipError_t e;
+  const size_t plane_bytes = size_t(b->ntot) * b->elem, buf_bytes = plane_bytes * b->q;
+  for (int k = 0; k < 2; ++k) {
+    e = hipMalloc(&b->buf[k], buf_bytes);
+    if (e != hipSuccess) return bail(e, "population buffer allocation");
+  }
+  if ((e = hipMalloc(&b->boxes_d, sizeof(BoxInfo) * nboxes)) != hipSuccess) return bail(e, "box table");
+  if ((e = hipMalloc(&b->tile_box_d, sizeof(uint32_t) * b->ntiles)) != hipSuccess) return bail(e, "tile table");
+  const bool dbl = b->store == F64;
+  const size_t rsz = dbl ? sizeof(Relax<double>) : sizeof(Relax<float>);
+  if ((e = hipMalloc(&b->relax_d, rsz * nboxes)) != hipSuccess) return bail(e, "relaxation table");
+  std::vector<char> rbytes(rsz * nboxes);
+  for (int k = 0; k < nboxes; ++k) {
+    auto fill = [&](auto *R) {
+      using CT = std::remove_reference_t<decltype(R->b6)>;
+      for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < 6; ++i) R->b2[j][i] = CT(rh[k].b2[j][i]);
+      for (int j = 0; j < 7; ++j)
+        for (int i = 0; i < 7; ++i) R->b3[j][i] = CT(rh[k].b3[j][i]);
+      for (int j = 0; j < 6; ++j)
+        for (int i = 0; i < 6; ++i) R->b4[j][i] = CT(rh[k].b4[j][i]);
+      for (int j = 0; j < 3; ++j)
+        for (int i = 0; i < 3; ++i) R->b5[j][i] = CT(rh[k].b5[j][i]);
+      R->b6 = CT(rh[k].b6);
+    };
+    if (dbl) fill(reinterpret_cast<Relax<double> *>(rbytes.data()) + k);
+    else fill(reinterpret_cast<Relax<float> *>(rbytes.data()) + k);
+  }
+  if (common->stream) {
+    b->stream = static_cast<hipStream_t>(common->stream);
+  } else {
+    if ((e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking)) != hipSuccess) return bail(e, "stream");
+    b->own_stream = true;
+  }
+  if ((e = hipMemcpy(b->boxes_d, b->boxes.data(), sizeof(BoxInfo) * nboxes, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "box table copy");
+  if ((e = hipMemcpy(b->tile_box_d, tb.data(), sizeof(uint32_t) * b->ntiles, hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "tile table copy");
+  if ((e = hipMemcpy(b->relax_d, rbytes.data(), rbytes.size(), hipMemcpyHostToDevice)) != hipSuccess)
+    return bail(e, "relaxation table copy");
+  *out = b;
+  return LBM_OK;
+}
+
+extern "C" void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  for (auto &kv : b->gcache) (void)hipGraphExecDestroy(kv.second);
+  for (int k = 0; k < 2; ++k)
+    if (b->buf[k]) (void)hipFree(b->buf[k]);
+  if (b->boxes_d) (void)hipFree(b->boxes_d);
+  if (b->tile_box_d) (void)hipFree(b->tile_box_d);
+  if (b->relax_d) (void)hipFree(b->relax_d);
+  if (b->staging) (void)hipFree(b->staging);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+extern "C" lbm_status lbm_batch_init_equilibrium(lbm_batch *b, const double *rho, const double *u) {
+  if (!b || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  const size_t n = b->ntot;
+  lbm_status s = batch_staging(b, 4 * n);
+  if (s != LBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(b->staging, rho, n * sizeof(double), hipMemcpyDefault, b->stream), "copy rho");
+  HIPCHECK(hipMemcpyAsync(b->staging + n, u, 3 * n * sizeof(double), hipMemcpyDefault, b->stream), "copy u");
+  b->t = 0;
+  b->cur = 0;
+  const void *fn = init_fn(b->s, b->store, b->space, MAXWELL, G_SHIFTED);
+  for (int k = 0; k < b->nboxes; ++k) {
+    FieldArgs a = batch_field(b, k, b->buf[0]);
+    a.rho_in = b->staging + b->boxes[k].off;
+    a.u_in = b->staging + n + 3 * size_t(b->boxes[k].off);
+    s = batch_launch_field(b, fn, a);
+    if (s != LBM_OK) return s;
+  }
+  HIPCHECK(hipStreamSynchronize(b->stream), "init sync");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!b->graphs || n < 2) {
+    for (int64_t k = 0; k < n; ++k) {
+      lbm_status s = batch_one_step(b);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  }
+  auto key = std::make_pair(n, b->cur);
+  auto it = b->gcache.find(key);
+  if (it == b->gcache.end()) {
+    const int cur0 = b->cur;
+    const int64_t t0 = b->t;
+    HIPCHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+    lbm_status s = LBM_OK;
+    for (int64_t k = 0; k < n && s == LBM_OK; ++k) s = batch_one_step(b);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->stream, &g);
+    b->cur = cur0;
+    b->t = t0;
+    if (s != LBM_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    it = b->gcache.emplace(key, ex).first;
+  }
+  HIPCHECK(hipGraphLaunch(it->second, b->stream), "graph launch");
+  b->cur ^= int(n & 1);
+  b->t += n;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u) {
+  if (!b || !rho || !u) return fail(LBM_EINVAL, "NULL argument");
+  const size_t n = b->ntot;
+  lbm_status s = batch_staging(b, 4 * n);
+  if (s != LBM_OK) return s;
+  const void *fn = macro_fn(b->s, b->store, G_SHIFTED);
+  for (int k = 0; k < b->nboxes; ++k) {
+    FieldArgs a = batch_field(b, k, b->buf[b->cur]);
+    a.rho_out = b->staging + b->boxes[k].off;
+    a.u_out = b->staging + n + 3 * size_t(b->boxes[k].off);
+    s = batch_launch_field(b, fn, a);
+    if (s != LBM_OK) return s;
+  }
+  HIPCHECK(hipMemcpyAsync(rho, b->staging, n * sizeof(double), hipMemcpyDefault, b->stream), "copy rho");
+  HIPCHECK(hipMemcpyAsync(u, b->staging + n, 3 * n * sizeof(double), hipMemcpyDefault, b->stream), "copy u");
+  HIPCHECK(hipStreamSynchronize(b->stream), "macroscopic sync");
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_get_populations(lbm_batch *b, double *df) {
+  if (!b || !df) return fail(LBM_EINVAL, "NULL argument");
+  const void *fn = export_fn(b->s, b->store, G_SHIFTED);
+  for (int k = 0; k < b->nboxes; ++k) {
+    const BoxInfo &B = b->boxes[k];
+    lbm_status s = batch_staging(b, size_t(b->q) * B.ncells);
+    if (s != LBM_OK) return s;
+    FieldArgs a = batch_field(b, k, b->buf[b->cur]);
+    a.pop = b->staging;
+    a.i0 = 0;
+    a.i1 = b->q;
+    s = batch_launch_field(b, fn, a);
+    if (s != LBM_OK) return s;
+    HIPCHECK(hipMemcpyAsync(df + size_t(b->q) * B.off, b->staging, size_t(b->q) * B.ncells * sizeof(double),
+                            hipMemcpyDefault, b->stream),
+             "copy populations");
+    HIPCHECK(hipStreamSynchronize(b->stream), "populations sync");
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_synchronize(lbm_batch *b) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  HIPCHECK(hipStreamSynchronize(b->stream), "synchronize");
+  return LBM_OK;
+}
+
+extern "C" int64_t lbm_batch_cells(const lbm_batch *b) { return b ? int64_t(b->ntot) : -1; }
+
+extern "C" lbm_status lbm_batch_set_graphs(lbm_batch *b, int enable) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  b->graphs = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms) {
+  if (!b || !ms) return fail(LBM_EINVAL, "NULL argument");
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  HIPCHECK(hipEventCreate(&e1), "event");
+  HIPCHECK(hipEventRecord(e0, b->stream), "event record");
+  lbm_status s = lbm_batch_step(b, n);
+  HIPCHECK(hipEventRecord(e1, b->stream), "event record");
+  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  float f = 0.f;
+  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = double(f);
+  return s;
+}

@@ -1,0 +1,286 @@
+"""GPU parity of the HIP sweep against the FP64 oracle, through the C ABI.
+
+Bars: FP64 populations within max |df_gpu - df_oracle| <= 1e-12 (after 100 steps where
+stated); integer index maps (streaming only) bit-exact; AA == pull, graph == host loop and
+checkpoint/resume bit-exact; FP32 relative L2 velocity error <= 1e-5 against the oracle.
+Grids span several launch tiles with ragged tails in x and y.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import lbm_workloads as W
+import oracle as O
+from paper_2211_02435_amd import lbm
+
+pytestmark = pytest.mark.gpu
+
+RAGGED3 = (70, 9, 5)     # two x-tiles of 64 with a tail of 6, y tail, 5 planes
+RAGGED2 = (70, 37, 1)
+
+
+def _rates(stencil, kind, seed=0):
+    if kind == "reg":
+        return O.regularized_rates(stencil, 1.7, omega_bulk=1.2)
+    rng = np.random.default_rng(seed)
+    om = rng.uniform(0.7, 1.9, O.stencil(stencil).q)
+    om[O.stencil(stencil).conserved] = 0.0
+    return om
+
+
+def _noisy_state(m, dims, seed=0, noise=2e-4):
+    nx, ny, nz = dims
+    rho, u = W.random_near_equilibrium_fields((nz, ny, nx), seed=seed, drho=5e-3, umax=0.04)
+    if m.st.d == 2:
+        u[2] = 0.0
+    df = O.init_equilibrium(m, rho, u)
+    return df + W.random_perturbation(m.st.q, (nz, ny, nx), seed=seed + 1, scale=noise)
+
+
+def _lattice(stencil, space, om, dims, **kw):
+    return lbm.Lattice(stencil, space, om, dims, **kw)
+
+
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("stencil,space", [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
+                                           ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
+                                           ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_init_equilibrium_matches_oracle(stencil, space, streaming):
+    dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
+    om = _rates(stencil, "reg")
+    rho, u = W.tgv3d_fields(dims[0], dims[1], dims[2], u0=0.05, period=16) if stencil != "D2Q9" \
+        else W.tgv2d_fields(dims[0], dims[1], 1, u0=0.05)
+    lat = _lattice(stencil, space, om, dims, storage="f64", streaming=streaming)
+    lat.lbm_init_equilibrium(rho, u)
+    got = lat.lbm_get_populations()
+    m = O.Method(stencil, space, om)
+    want = O.init_equilibrium(m, rho, u)
+    assert np.abs(got - want).max() <= 4e-15
+    r2, u2 = lat.lbm_macroscopic()
+    assert np.abs(r2 - rho).max() <= 1e-15
+    d = 3 if stencil != "D2Q9" else 2
+    assert np.abs(u2[:d] - u[:d]).max() <= 1e-15
+
+
+@pytest.mark.parametrize("stencil,space", [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
+                                           ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
+                                           ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")])
+@pytest.mark.parametrize("kind", ["reg", "gen"])
+def test_sweep_fp64_matches_oracle(stencil, space, kind):
+    """Non-equilibrium start (equilibrium + noise from the oracle), 4 steps, FP64."""
+    dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
+    om = _rates(stencil, kind, seed=3)
+    m = O.Method(stencil, space, om)
+    df0 = _noisy_state(m, dims, seed=11)
+    lat = _lattice(stencil, space, om, dims, storage="f64")
+    lat.lbm_set_populations(df0)
+    lat.lbm_step(4)
+    got = lat.lbm_get_populations()
+    want = O.step(m, df0, 4)
+    err = np.abs(got - want).max()
+    print("%s %s %s max|d df| = %.3e" % (stencil, space, kind, err))
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("stencil,space,kind", [("D2Q9", "central", "reg"), ("D3Q19", "raw", "reg"),
+                                                ("D3Q27", "cumulant", "reg"), ("D3Q27", "cumulant", "gen"),
+                                                ("D3Q27", "central", "reg")])
+def test_sweep_fp64_100_steps(stencil, space, kind):
+    """Taylor-Green start, 100 steps, FP64: max |d df| <= 1e-12."""
+    dims = (20, 12, 9) if stencil != "D2Q9" else RAGGED2
+    om = _rates(stencil, kind, seed=5) if kind == "gen" else O.regularized_rates(stencil, 1.9699)
+    if stencil == "D2Q9":
+        rho, u = W.tgv2d_fields(dims[0], dims[1], 1, u0=0.02)
+    else:
+        rho, u = W.tgv3d_fields(dims[0], dims[1], dims[2], u0=0.05, period=12)
+    lat = _lattice(stencil, space, om, dims, storage="f64")
+    lat.lbm_init_equilibrium(rho, u)
+    lat.lbm_step(100)
+    got = lat.lbm_get_populations()
+    m = O.Method(stencil, space, om)
+    want = O.step(m, O.init_equilibrium(m, rho, u), 100)
+    err = np.abs(got - want).max()
+    print("%s %s %s 100 steps max|d df| = %.3e" % (stencil, space, kind, err))
+    assert err <= 1e-12
+
+
+def test_config_d2q9_central_64_taylor_green():
+    """D2Q9 central moments, 64^2, u0 = 0.01, omega_s = 1.6, other rates 1, FP64: parity at
+    step 100 and the velocity amplitude decays as exp(-2 nu k^2 t) over 1000 steps."""
+    n = 64
+    om = O.regularized_rates("D2Q9", 1.6)
+    rho, u = W.tgv2d_fields(n, n, 1, u0=0.01)
+    lat = _lattice("D2Q9", "central", om, (n, n, 1), storage="f64")
+    lat.lbm_init_equilibrium(rho, u)
+    lat.lbm_step(100)
+    m = O.Method("D2Q9", "central", om)
+    df = O.step(m, O.init_equilibrium(m, rho, u), 100)
+    assert np.abs(lat.lbm_get_populations() - df).max() <= 1e-12
+    lat.lbm_step(900)
+    _, ug = lat.lbm_macroscopic()
+    k = 2 * math.pi / n
+    x = np.arange(n)
+    ref = np.cos(k * x)[None, :] * np.sin(k * x)[:, None]
+    amp = (ug[0, 0] * ref).sum() / (ref * ref).sum() / 0.01
+    nu = O.omega_to_viscosity(1.6)
+    want = math.exp(-2 * nu * k * k * 1000)
+    assert abs(amp / want - 1) < 1e-2, (amp, want)
+
+
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+@pytest.mark.parametrize("n", [1, 2, 5])
+def test_streaming_index_maps_bit_exact(stencil, streaming, n):
+    """Identity collision: n steps of streaming equal numpy.roll bit for bit."""
+    dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
+    q = O.stencil(stencil).q
+    rng = np.random.default_rng(7)
+    df = rng.integers(-1000, 1000, size=(q, dims[2], dims[1], dims[0])).astype(np.float64) / 1024.0
+    lat = _lattice(stencil, "raw", _rates(stencil, "reg"), dims, storage="f32", streaming=streaming)
+    lat.lbm_set_populations(df)
+    lat.lbm_debug_stream_only(n)
+    got = lat.lbm_get_populations()
+    m = O.Method(stencil, "raw", np.zeros(q))
+    want = df
+    for _ in range(n):
+        want = O.stream(m, want)
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("n", [3, 4])
+def test_aa_equals_pull(storage, n):
+    dims = RAGGED3
+    om = _rates("D3Q27", "reg")
+    rho, u = W.tgv3d_fields(*dims, u0=0.05, period=16)
+    outs = []
+    for streaming in ("pull", "aa"):
+        lat = _lattice("D3Q27", "cumulant", om, dims, storage=storage, streaming=streaming)
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_step(n)
+        outs.append(lat.lbm_get_populations())
+    np.testing.assert_array_equal(outs[0], outs[1])
+
+
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_graph_equals_host_loop_and_checkpoint(streaming):
+    dims = RAGGED3
+    om = _rates("D3Q27", "gen", seed=9)
+    rho, u = W.tgv3d_fields(*dims, u0=0.05, period=16)
+    a = _lattice("D3Q27", "cumulant", om, dims, storage="f32", streaming=streaming)
+    b = _lattice("D3Q27", "cumulant", om, dims, storage="f32", streaming=streaming)
+    for lat in (a, b):
+        lat.lbm_init_equilibrium(rho, u)
+    a.lbm_set_graphs(True)
+    b.lbm_set_graphs(False)
+    a.lbm_step(7)
+    b.lbm_step(7)
+    pa = a.lbm_get_populations()
+    np.testing.assert_array_equal(pa, b.lbm_get_populations())
+    # replay the cached graph twice more, with host work in between
+    a.lbm_step(7)
+    _ = a.lbm_diagnostics()
+    a.lbm_step(7)
+    b.lbm_step(14)
+    np.testing.assert_array_equal(a.lbm_get_populations(), b.lbm_get_populations())
+    assert a.lbm_time() == 21
+    # checkpoint / resume: restore step 7 into a fresh context and advance 14 more
+    c = _lattice("D3Q27", "cumulant", om, dims, storage="f32", streaming=streaming)
+    c.lbm_set_populations(pa)
+    c.lbm_set_time(7)
+    c.lbm_step(14)
+    np.testing.assert_array_equal(c.lbm_get_populations(), a.lbm_get_populations())
+
+
+def test_diagnostics_match_oracle_and_detect_nonfinite():
+    dims = (20, 12, 9)
+    om = _rates("D3Q27", "reg")
+    rho, u = W.tgv3d_fields(*dims, u0=0.05, period=12)
+    lat = _lattice("D3Q27", "cumulant", om, dims, storage="f64")
+    lat.lbm_init_equilibrium(rho, u)
+    lat.lbm_step(3)
+    d = lat.lbm_diagnostics()
+    m = O.Method("D3Q27", "cumulant", om)
+    want = O.diagnostics(m, O.step(m, O.init_equilibrium(m, rho, u), 3))
+    np.testing.assert_allclose(d[[0, 4]], want[[0, 4]], rtol=1e-12)
+    np.testing.assert_allclose(d[1:4], want[1:4], rtol=0, atol=1e-12)
+    assert d[5] == 0
+    df = lat.lbm_get_populations()
+    df[3, 1, 2, 3] = np.nan
+    df[0, 0, 0, 0] = np.inf
+    lat.lbm_set_populations(df)
+    d2 = lat.lbm_diagnostics(allow_nonfinite=True)
+    assert d2[5] == 2
+    with pytest.raises(lbm.LbmError):
+        lat.lbm_diagnostics()
+
+
+def test_fp32_velocity_error_cumulant():
+    """D3Q27 cumulant, Taylor-Green u0 = 0.05, omega_s = 1.969902 (the 512^3 constants), 16^3,
+    200 steps, FP32 storage and compute: relative L2 velocity error vs the FP64 oracle <= 1e-5."""
+    n, steps = 16, 200
+    om = O.regularized_rates("D3Q27", W.re_to_omega(0.05, 512, 1600.0))
+    rho, u = W.tgv3d_fields(n, u0=0.05)
+    lat = _lattice("D3Q27", "cumulant", om, (n, n, n), storage="f32")
+    lat.lbm_init_equilibrium(rho, u)
+    lat.lbm_step(steps)
+    _, ug = lat.lbm_macroscopic()
+    m = O.Method("D3Q27", "cumulant", om)
+    _, uo = O.macroscopic(m, O.step(m, O.init_equilibrium(m, rho, u), steps))
+    rel = np.linalg.norm(ug - uo) / np.linalg.norm(uo)
+    print("FP32 cumulant 16^3 x 200: relative L2 velocity error %.3e" % rel)
+    assert rel <= 1e-5
+
+
+def test_swe_fp64_parity_and_fp16_error():
+    """Shallow water (Zhou equilibrium, central moments), 96 x 80, g = 0.1, omega_s = 0.695652."""
+    dims = (96, 80, 1)
+    om = O.regularized_rates("D2Q9", 1.0 / (3 * 0.3125 + 0.5))
+    h, u = W.swe_bumps(96, seed=0, sigma=(4.0, 12.0))
+    h, u = h[:, :80, :], u[:, :, :80, :]
+    h, u = np.ascontiguousarray(h), np.ascontiguousarray(u)
+    m = O.Method("D2Q9", "central", om, equilibrium="swe", gravity=0.1)
+    want = O.step(m, O.init_equilibrium(m, h, u), 100)
+    lat = _lattice("D2Q9", "central", om, dims, storage="f64", equilibrium="swe", gravity=0.1)
+    lat.lbm_init_equilibrium(h, u)
+    lat.lbm_step(100)
+    assert np.abs(lat.lbm_get_populations() - want).max() <= 1e-12
+    l16 = _lattice("D2Q9", "central", om, dims, storage="f16", equilibrium="swe", gravity=0.1)
+    l16.lbm_init_equilibrium(h, u)
+    l16.lbm_step(100)
+    h16, u16 = l16.lbm_macroscopic()
+    ho, uo = O.macroscopic(m, want)
+    rel = np.linalg.norm(u16[:2] - uo[:2]) / np.linalg.norm(uo[:2])
+    print("SWE FP16 storage relative L2 velocity error after 100 steps: %.3e" % rel)
+    assert rel <= 2e-2
+    assert np.abs(h16 - ho).max() <= 2e-3
+
+
+# ------------------------------------------------------------------------------------------
+def test_batch_matches_single_boxes_and_oracle():
+    boxes = [(16, 16, 16), (12, 12, 12), (20, 20, 20)]
+    rates = [O.regularized_rates("D3Q27", w) for w in (1.9, 1.3, 1.6)]
+    fields = [W.tgv3d_fields(d[0], u0=0.03 + 0.01 * k, phase=(0.1 * k, 0.2, 0.3)) for k, d in enumerate(boxes)]
+    rho_cat = np.concatenate([f[0].ravel() for f in fields])
+    u_cat = np.concatenate([f[1].ravel() for f in fields])
+    for storage in ("f64", "f32"):
+        bat = lbm.Batch("D3Q27", "central", boxes, rates, storage=storage)
+        bat.lbm_batch_init_equilibrium(rho_cat, u_cat)
+        bat.lbm_batch_step(5)
+        got = bat.lbm_batch_get_populations()
+        off = 0
+        for d, om, (rho, u) in zip(boxes, rates, fields):
+            lat = _lattice("D3Q27", "central", om, d, storage=storage)
+            lat.lbm_init_equilibrium(rho, u)
+            lat.lbm_step(5)
+            single = lat.lbm_get_populations().ravel()
+            mine = got[off:off + single.size]
+            assert np.abs(mine - single).max() <= (1e-15 if storage == "f64" else 1e-7)
+            if storage == "f64":
+                m = O.Method("D3Q27", "central", om)
+                want = O.step(m, O.init_equilibrium(m, rho, u), 5).ravel()
+                assert np.abs(mine - want).max() <= 1e-13
+            off += single.size
