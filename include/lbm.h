@@ -42,7 +42,8 @@
  *     used exactly (they do not depend on u).  LBM_EQ_SHALLOW_WATER is the discrete D2Q9
  *     equilibrium of Zhou (sec. 5.2) with the listing's -u.u/6 term; `gravity` is g.
  *
- * Memory layout of every field argument: SoA, x fastest.
+ * Memory layout of every field argument: SoA, x fastest (the device population buffers use
+ * the same order with a padded plane stride, see lbm_required_bytes).
  *   cell(x, y, z) = (z * ny + y) * nx + x, ncells = nx * ny * nz
  *   populations  df[i * ncells + cell]          (canonical pre-collision df(t), FP64)
  *   density      rho[cell]   (water height h for the shallow-water equilibrium)
@@ -122,7 +123,9 @@ lbm_status lbm_params_default(lbm_params *p);
 lbm_status lbm_validate(const lbm_params *p);
 
 /* Bytes of device population storage the parameter set needs in total (both arrays for
- * pull, one for AA): nbuffers * q * ncells * sizeof(storage).  Pure host code. */
+ * pull, one for AA): nbuffers * q * plane * sizeof(storage), where the plane stride is ncells
+ * rounded up to 256 bytes plus a padding that staggers the q planes across HBM channels
+ * (environment variable LBM_PLANE_PAD_BYTES overrides the padding).  Pure host code. */
 lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes);
 
 /* Create a context: validate, derive the relaxation matrix in monomial form, allocate or
@@ -139,6 +142,10 @@ lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *u
  * With graphs enabled (default) the n launches are recorded once into a hipGraph per
  * (n, buffer parity) and replayed. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Record (without running) the hipGraph that the next lbm_step(n) will replay, so that the
+ * recording cost stays out of a timed region.  No effect for n < 2 or with graphs off. */
+lbm_status lbm_graph_prepare(lbm_ctx *ctx, int64_t n);
 
 /* Density (or h) and velocity of df(t), FP64, synchronous. */
 lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho, double *u);
@@ -204,6 +211,7 @@ lbm_status lbm_batch_create(const lbm_params *common, int nboxes, const int64_t 
 void lbm_batch_destroy(lbm_batch *b);
 lbm_status lbm_batch_init_equilibrium(lbm_batch *b, const double *rho, const double *u);
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+lbm_status lbm_batch_graph_prepare(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u);
 lbm_status lbm_batch_get_populations(lbm_batch *b, double *df);
 lbm_status lbm_batch_synchronize(lbm_batch *b);

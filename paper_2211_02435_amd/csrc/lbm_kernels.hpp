@@ -28,7 +28,7 @@ struct SweepArgs {
   const ST *src;
   ST *dst;
   int nx, ny, nz;
-  uint32_t ncells;   // plane stride in elements (ncells * sizeof(ST) < 2^32)
+  uint32_t plane;    // population plane stride in elements (plane * sizeof(ST) < 2^32)
   int tiles_x, tiles_y;
   int swizzle;       // nonzero: consecutive tiles on one XCD
   CT grav;
@@ -123,11 +123,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     if constexpr (PAT == PULL) {
-      g[L::gidx(i)] = CT(ld(a.src, a.ncells, i, nb.at(cx, cy, cz, -1)));
+      g[L::gidx(i)] = CT(ld(a.src, a.plane, i, nb.at(cx, cy, cz, -1)));
     } else if constexpr (PAT == AA_EVEN) {
-      g[L::gidx(i)] = CT(ld(a.src, a.ncells, i, self));
+      g[L::gidx(i)] = CT(ld(a.src, a.plane, i, self));
     } else {
-      g[L::gidx(i)] = CT(ld(a.src, a.ncells, L::opp(i), nb.at(cx, cy, cz, -1)));
+      g[L::gidx(i)] = CT(ld(a.src, a.plane, L::opp(i), nb.at(cx, cy, cz, -1)));
     }
   });
 
@@ -138,11 +138,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     const ST v = ST(g[L::gidx(i)]);
     if constexpr (PAT == PULL) {
-      st(a.dst, a.ncells, i, self, v);
+      st(a.dst, a.plane, i, self, v);
     } else if constexpr (PAT == AA_EVEN) {
-      st(a.dst, a.ncells, L::opp(i), self, v);
+      st(a.dst, a.plane, L::opp(i), self, v);
     } else {
-      st(a.dst, a.ncells, i, nb.at(cx, cy, cz, +1), v);
+      st(a.dst, a.plane, i, nb.at(cx, cy, cz, +1), v);
     }
   });
 }

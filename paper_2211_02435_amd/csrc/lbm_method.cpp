@@ -2,6 +2,7 @@
 //
 // Pure host code (no HIP runtime calls), so the CPU test suite can exercise it without a GPU.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -21,6 +22,20 @@ lbm_status fail(lbm_status s, const std::string &msg) {
 int stencil_q(int s) { return s == LBM_D2Q9 ? 9 : (s == LBM_D3Q19 ? 19 : 27); }
 int stencil_d(int s) { return s == LBM_D2Q9 ? 2 : 3; }
 size_t storage_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
+
+// Population plane stride in elements: ncells plus a padding that staggers the start of the
+// q planes across HBM channels (a power-of-two plane size puts all q streams of a cell on
+// the same channel offset).  LBM_PLANE_PAD_BYTES overrides the default padding.
+size_t plane_elems(const lbm_params *p) {
+  const size_t ncells = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
+  const size_t eb = storage_bytes(p->storage);
+  size_t pad_bytes = kDefaultPlanePadBytes;
+  if (const char *env = std::getenv("LBM_PLANE_PAD_BYTES")) pad_bytes = size_t(std::strtoull(env, nullptr, 10));
+  // keep every plane 256-byte aligned
+  const size_t align = 256 / eb;
+  const size_t base = (ncells + align - 1) / align * align;
+  return base + (pad_bytes / 256) * align;
+}
 
 int resolve_eq_form(const lbm_params *p) {
   if (p->eq_form != LBM_EQFORM_DEFAULT) return p->eq_form;
@@ -225,7 +240,7 @@ lbm_status validate(const lbm_params *p) {
   if (!p->periodic[0] || !p->periodic[1] || !p->periodic[2])
     return fail(LBM_EUNSUPPORTED, "only periodic boundaries are implemented");
   const double ncells = double(p->nx) * double(p->ny) * double(p->nz);
-  if (ncells * double(storage_bytes(p->storage)) >= 4294967296.0)
+  if (double(plane_elems(p)) * double(storage_bytes(p->storage)) >= 4294967296.0)
     return fail(LBM_EUNSUPPORTED, "one population plane must stay below 4 GiB (32-bit offsets)");
   if (p->nx > 2147483647 || p->ny > 2147483647 || p->nz > 2147483647) return fail(LBM_EINVAL, "dims too large");
   return LBM_OK;
@@ -262,8 +277,7 @@ extern "C" lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes) {
   if (s != LBM_OK) return s;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
   const size_t nbuf = p->streaming == LBM_STREAM_PULL ? 2 : 1;
-  *bytes = nbuf * size_t(stencil_q(p->stencil)) * size_t(p->nx) * size_t(p->ny) * size_t(p->nz) *
-           storage_bytes(p->storage);
+  *bytes = nbuf * size_t(stencil_q(p->stencil)) * plane_elems(p) * storage_bytes(p->storage);
   return LBM_OK;
 }
 

@@ -23,6 +23,8 @@ int stencil_q(int s);
 int stencil_d(int s);
 size_t storage_bytes(int st);
 int resolve_eq_form(const lbm_params *p);
+size_t plane_elems(const lbm_params *p);
+constexpr size_t kDefaultPlanePadBytes = 0;
 lbm_status validate(const lbm_params *p);
 lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out);
 

@@ -98,6 +98,7 @@ struct lbm_ctx {
   int s = 0, q = 0, d = 0, space = 0, eq = 0, store = 0, pattern = 0;
   int nx = 1, ny = 1, nz = 1;
   uint32_t ncells = 0;
+  uint32_t plane = 0;   // population plane stride (elements), >= ncells
   size_t elem = 4;
   RelaxHost R{};
   bool reg = false;
@@ -129,7 +130,7 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
-  a.ncells = c->ncells;
+  a.plane = c->plane;
   a.tiles_x = (c->nx + c->bx - 1) / c->bx;
   a.tiles_y = (c->ny + c->by - 1) / c->by;
   a.swizzle = c->swz;
@@ -201,7 +202,7 @@ static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
   FieldArgs a;
   std::memset(&a, 0, sizeof(a));
   a.buf = buf;
-  a.plane = c->ncells;
+  a.plane = c->plane;
   a.ncells = c->ncells;
   a.nx = c->nx;
   a.ny = c->ny;
@@ -282,7 +283,8 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   }
   c->reg = c->R.regularized;
   c->nbuf = c->pattern == LBM_STREAM_PULL ? 2 : 1;
-  c->plane_bytes = size_t(c->ncells) * c->elem;
+  c->plane = uint32_t(plane_elems(p));
+  c->plane_bytes = size_t(c->plane) * c->elem;
   c->buf_bytes = c->plane_bytes * size_t(c->q);
   for (int k = 0; k < c->nbuf; ++k) {
     if (p->buffers[k]) {
@@ -370,17 +372,9 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const 
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
-  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
-  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  if (n == 0) return LBM_OK;
-  if (!c->graphs || n < 2) {
-    for (int64_t k = 0; k < n; ++k) {
-      lbm_status s = one_step(c);
-      if (s != LBM_OK) return s;
-    }
-    return LBM_OK;
-  }
+namespace lbm {
+// the cached hipGraph that replays n sweeps from the current buffer parity (recorded once)
+static lbm_status graph_for(lbm_ctx *c, int64_t n, hipGraphExec_t *out) {
   const int parity = c->pattern == LBM_STREAM_PULL ? c->cur : int(c->t % 2);
   auto key = std::make_pair(n, parity);
   auto it = c->gcache.find(key);
@@ -405,10 +399,36 @@ extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     it = c->gcache.emplace(key, ex).first;
   }
-  HIPCHECK(hipGraphLaunch(it->second, c->stream), "graph launch");
+  *out = it->second;
+  return LBM_OK;
+}
+}  // namespace lbm
+
+extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!c->graphs || n < 2) {
+    for (int64_t k = 0; k < n; ++k) {
+      lbm_status s = one_step(c);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  }
+  hipGraphExec_t ex = nullptr;
+  lbm_status s = graph_for(c, n, &ex);
+  if (s != LBM_OK) return s;
+  HIPCHECK(hipGraphLaunch(ex, c->stream), "graph launch");
   if (c->pattern == LBM_STREAM_PULL) c->cur ^= int(n & 1);
   c->t += n;
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_graph_prepare(lbm_ctx *c, int64_t n) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (n < 2 || !c->graphs) return LBM_OK;
+  hipGraphExec_t ex = nullptr;
+  return graph_for(c, n, &ex);
 }
 
 extern "C" lbm_status lbm_debug_stream_only(lbm_ctx *c, int64_t n) {
@@ -1003,17 +1023,8 @@ extern "C" lbm_status lbm_batch_init_equilibrium(lbm_batch *b, const double *rho
   return LBM_OK;
 }
 
-extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
-  if (!b) return fail(LBM_EINVAL, "batch is NULL");
-  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
-  if (n == 0) return LBM_OK;
-  if (!b->graphs || n < 2) {
-    for (int64_t k = 0; k < n; ++k) {
-      lbm_status s = batch_one_step(b);
-      if (s != LBM_OK) return s;
-    }
-    return LBM_OK;
-  }
+namespace lbm {
+static lbm_status batch_graph_for(lbm_batch *b, int64_t n, hipGraphExec_t *out) {
   auto key = std::make_pair(n, b->cur);
   auto it = b->gcache.find(key);
   if (it == b->gcache.end()) {
@@ -1037,10 +1048,36 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
     if (e != hipSuccess) return hip_fail(e, "graph instantiate");
     it = b->gcache.emplace(key, ex).first;
   }
-  HIPCHECK(hipGraphLaunch(it->second, b->stream), "graph launch");
+  *out = it->second;
+  return LBM_OK;
+}
+}  // namespace lbm
+
+extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
+  if (n == 0) return LBM_OK;
+  if (!b->graphs || n < 2) {
+    for (int64_t k = 0; k < n; ++k) {
+      lbm_status s = batch_one_step(b);
+      if (s != LBM_OK) return s;
+    }
+    return LBM_OK;
+  }
+  hipGraphExec_t ex = nullptr;
+  lbm_status s = batch_graph_for(b, n, &ex);
+  if (s != LBM_OK) return s;
+  HIPCHECK(hipGraphLaunch(ex, b->stream), "graph launch");
   b->cur ^= int(n & 1);
   b->t += n;
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_graph_prepare(lbm_batch *b, int64_t n) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (n < 2 || !b->graphs) return LBM_OK;
+  hipGraphExec_t ex = nullptr;
+  return batch_graph_for(b, n, &ex);
 }
 
 extern "C" lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u) {

@@ -47,6 +47,7 @@ SIGNATURES = {
     "lbm_destroy": (None, [c_void_p]),
     "lbm_init_equilibrium": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_step": (c_int, [c_void_p, c_int64]),
+    "lbm_graph_prepare": (c_int, [c_void_p, c_int64]),
     "lbm_macroscopic": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_get_populations": (c_int, [c_void_p, c_void_p]),
     "lbm_set_populations": (c_int, [c_void_p, c_void_p]),
@@ -66,6 +67,7 @@ SIGNATURES = {
     "lbm_batch_destroy": (None, [c_void_p]),
     "lbm_batch_init_equilibrium": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_batch_step": (c_int, [c_void_p, c_int64]),
+    "lbm_batch_graph_prepare": (c_int, [c_void_p, c_int64]),
     "lbm_batch_macroscopic": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_batch_get_populations": (c_int, [c_void_p, c_void_p]),
     "lbm_batch_synchronize": (c_int, [c_void_p]),
@@ -192,6 +194,9 @@ class Lattice:
     def lbm_step(self, n=1):
         check(self.lib.lbm_step(self.ctx, int(n)))
 
+    def lbm_graph_prepare(self, n):
+        check(self.lib.lbm_graph_prepare(self.ctx, int(n)))
+
     def lbm_debug_stream_only(self, n=1):
         check(self.lib.lbm_debug_stream_only(self.ctx, int(n)))
 
@@ -287,6 +292,9 @@ class Batch:
 
     def lbm_batch_step(self, n=1):
         check(self.lib.lbm_batch_step(self.b, int(n)))
+
+    def lbm_batch_graph_prepare(self, n):
+        check(self.lib.lbm_batch_graph_prepare(self.b, int(n)))
 
     def lbm_batch_macroscopic(self):
         n = sum(self.ncells)

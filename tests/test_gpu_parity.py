@@ -205,7 +205,11 @@ def test_diagnostics_match_oracle_and_detect_nonfinite():
     d = lat.lbm_diagnostics()
     m = O.Method("D3Q27", "cumulant", om)
     want = O.diagnostics(m, O.step(m, O.init_equilibrium(m, rho, u), 3))
-    np.testing.assert_allclose(d[[0, 4]], want[[0, 4]], rtol=1e-12)
+    # mass is conserved exactly up to round-off: compare with the input fields themselves;
+    # the oracle's dense solves in absolute populations drift by ~1e-16 per cell and step
+    assert abs(d[0] - math.fsum((rho - 1.0).ravel())) <= 1e-13
+    np.testing.assert_allclose(d[0], want[0], rtol=1e-11)
+    np.testing.assert_allclose(d[4], want[4], rtol=1e-12)
     np.testing.assert_allclose(d[1:4], want[1:4], rtol=0, atol=1e-12)
     assert d[5] == 0
     df = lat.lbm_get_populations()
