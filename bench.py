@@ -57,9 +57,10 @@ def build_workload(name):
     return cfg
 
 
-def run_box(lbm, stencil, space, om, dims, storage, rho, u, steps, warmup, autotune, streaming="pull"):
+def run_box(lbm, stencil, space, om, dims, storage, rho, u, steps, warmup, autotune, streaming="pull",
+            layout="auto"):
     import torch
-    lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming)
+    lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming, layout=layout)
     lat.lbm_init_equilibrium(rho, u)
     if autotune:
         lat.lbm_autotune()
@@ -111,6 +112,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--layout", default="auto", choices=["auto", "planes", "rows"])
+    ap.add_argument("--streaming", default="pull", choices=["pull", "aa"])
     ap.add_argument("--cpu-size", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=40)
     args = ap.parse_args()
@@ -137,7 +140,7 @@ def main():
 
     # FP32 (value)
     lat32, wall32, ev32 = run_box(lbm, stencil, space, om, dims, "f32", rho, u, args.steps, args.warmup,
-                                  not args.no_autotune)
+                                  not args.no_autotune, args.streaming, args.layout)
     mlups32 = cells * args.steps / wall32 / 1e6
     bytes32 = 2 * q * 4 * cells
     t_launch32 = ev32 / 1e3 / args.steps
@@ -149,7 +152,7 @@ def main():
     vel_err = None
     if not args.no_fp64:
         lat64, wall64, ev64 = run_box(lbm, stencil, space, om, dims, "f64", rho, u, args.steps, args.warmup,
-                                      not args.no_autotune)
+                                      not args.no_autotune, args.streaming, args.layout)
         t_launch64 = ev64 / 1e3 / args.steps
         result_fp64 = {"mlups": cells * args.steps / wall64 / 1e6,
                        "ms_per_step": wall64 * 1e3 / args.steps,
@@ -177,8 +180,8 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(stencil, space, om, args.cpu_size, args.cpu_steps)
 
-    workload = "%s %s %d^3 periodic Taylor-Green (u0 %.2f, omega_s %.6f, other rates 1), pull" % (
-        stencil, space, n, cfg["u0"], cfg["omega_shear"])
+    workload = "%s %s %d^3 periodic Taylor-Green (u0 %.2f, omega_s %.6f, other rates 1), %s" % (
+        stencil, space, n, cfg["u0"], cfg["omega_shear"], args.streaming)
     out = {
         "metric": "MLUPS and % of HBM roofline, D3Q27 cumulant 512^3, FP32 vs FP64",
         "value": mlups32,
@@ -193,7 +196,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic Taylor-Green vortex initial fields",
         "config": {"workload": workload, "cells": cells, "stencil": stencil, "space": space,
-                   "storage": "f32", "streaming": "pull", "launch": launch32},
+                   "storage": "f32", "streaming": args.streaming, "layout": args.layout, "launch": launch32},
         "roofline": {"bound": "hbm", "achieved": achieved32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved32 / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload if n == cfg["dims"][0] else "none", cells),

@@ -90,6 +90,12 @@ typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_sto
  * x + xi_i); sec. 4.4. */
 typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1 } lbm_streaming;
 
+/* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
+ * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
+ * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS for F32 and
+ * F16 storage, PLANES for F64 (the faster layout measured for each on MI355X). */
+typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 } lbm_layout;
+
 typedef struct {
   int stencil;            /* lbm_stencil                                                      */
   int space;              /* lbm_space                                                        */
@@ -106,12 +112,13 @@ typedef struct {
   void *buffers[2];       /* optional caller-owned device buffers (e.g. torch allocations);   */
   size_t buffer_bytes;    /* each >= lbm_required_bytes / nbuffers; NULL -> library allocates */
   void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
+  int layout;             /* lbm_layout of the device population buffers                      */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fill *p with defaults: D3Q27, cumulant, Maxwellian, DEFAULT form, zero-centred, FP32, pull,
- * periodic, 1x1x1, no rates.  Always succeeds for non-NULL p. */
+ * periodic, 1x1x1, no rates, AUTO layout.  Always succeeds for non-NULL p. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Validate a parameter set without touching any device (pure host code).
@@ -123,9 +130,11 @@ lbm_status lbm_params_default(lbm_params *p);
 lbm_status lbm_validate(const lbm_params *p);
 
 /* Bytes of device population storage the parameter set needs in total (both arrays for
- * pull, one for AA): nbuffers * q * plane * sizeof(storage), where the plane stride is ncells
- * rounded up to 256 bytes plus a padding that staggers the q planes across HBM channels
- * (environment variable LBM_PLANE_PAD_BYTES overrides the padding).  Pure host code. */
+ * pull, one for AA).  PLANES: nbuffers * q * plane * sizeof(storage), the plane stride being
+ * ncells rounded up to 256 bytes plus a padding that staggers the q planes across HBM
+ * channels (environment variable LBM_PLANE_PAD_BYTES overrides the padding).  ROWS:
+ * nbuffers * nz * ny * q * nxp * sizeof(storage), nxp = nx rounded up to 256 bytes.
+ * Pure host code. */
 lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes);
 
 /* Create a context: validate, derive the relaxation matrix in monomial form, allocate or

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(BATCH_THREADS) batch_sweep_kernel(BatchArgs<ST
   const uint32_t r = c - uint32_t(z) * nxy;
   const int y = int(r / uint32_t(B.nx));
   const int x = int(r - uint32_t(y) * uint32_t(B.nx));
-  const Nbr<L::D> nb(x, y, z, B.nx, B.ny, B.nz);
+  const NbrNat<L::D> nb(x, y, z, B.nx, B.ny, B.nz);
   const ST *src = a.src + B.off;
   ST *dst = a.dst + B.off;
 

@@ -7,9 +7,12 @@
 // macro_kernel   density and velocity of df(t) (eq. DensityAndVelocityFromDeviation)
 // diag_kernel    FP64 mass / momentum / kinetic-energy / non-finite reductions
 //
-// Storage is SoA: population i of cell c at buf[i * ncells + c], x fastest.  One thread owns
-// one cell; a block covers bx cells along x and by rows along y of one z-plane.  Periodic
-// neighbours come from per-axis wrapped coordinates (integer selects only).
+// Storage is SoA with x fastest, either one plane per population or the q populations of a
+// row side by side (Strides).  One thread owns one cell; a block covers bx cells along x and
+// by rows along y of one z-plane.  Periodic neighbours come from per-axis wrapped
+// coordinates (integer selects only).  Stores are non-temporal: every population written in
+// a sweep is read again only in the next sweep, after the whole 2 Q sizeof(ST) ncells bytes
+// have streamed through the caches.
 #pragma once
 
 #include "lbm_device.hpp"
@@ -23,12 +26,24 @@ template <> struct StoreTraits<F64> { using S = double;   using C = double; };
 template <> struct StoreTraits<F32> { using S = float;    using C = float; };
 template <> struct StoreTraits<F16> { using S = _Float16; using C = float; };
 
+// Storage layout: population i of cell (x, y, z) lives at element
+//   i * ps + z * zs + y * ys + x
+// planes layout: ps = plane (>= ncells, padded), zs = ny * nx, ys = nx
+// rows layout:   ps = nxp (nx rounded up), ys = q * nxp, zs = ny * ys  (all q populations of
+//                one row side by side, so a block touches a few contiguous rows per plane)
+// Per block z is uniform, so i * ps + z * zs is a scalar 64-bit base and y * ys + x the
+// 32-bit per-lane offset (bounded by zs < 2^32 elements of a z-plane).
+struct Strides {
+  uint64_t ps, zs;
+  uint32_t ys;
+};
+
 template <class ST, class CT>
 struct SweepArgs {
   const ST *src;
   ST *dst;
   int nx, ny, nz;
-  uint32_t plane;    // population plane stride in elements (plane * sizeof(ST) < 2^32)
+  Strides L;
   int tiles_x, tiles_y;
   int swizzle;       // nonzero: consecutive tiles on one XCD
   CT grav;
@@ -63,48 +78,70 @@ __device__ __forceinline__ CellPos tile_cell(int nx, int ny, int tiles_x, int ti
   return p;
 }
 
-// neighbour tables of one cell: rows[dy+1][dz+1] = (zw * ny + yw) * nx, xs[dx+1] = xw
+// periodic neighbours of one cell in a strided buffer
 template <int D>
 struct Nbr {
-  uint32_t rows[3][3];
-  uint32_t xs[3];
-  __device__ __forceinline__ Nbr(int x, int y, int z, int nx, int ny, int nz) {
+  uint64_t zoff[3];  // (z + dz wrapped) * zs, block-uniform
+  uint32_t yoff[3];  // (y + dy wrapped) * ys
+  uint32_t xs[3];    // x + dx wrapped
+  __device__ __forceinline__ Nbr(int x, int y, int z, int nx, int ny, int nz, const Strides &L) {
     xs[0] = uint32_t(x == 0 ? nx - 1 : x - 1);
     xs[1] = uint32_t(x);
     xs[2] = uint32_t(x == nx - 1 ? 0 : x + 1);
-    const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-    const int yy[3] = {ym, y, yp};
+    yoff[0] = uint32_t(y == 0 ? ny - 1 : y - 1) * L.ys;
+    yoff[1] = uint32_t(y) * L.ys;
+    yoff[2] = uint32_t(y == ny - 1 ? 0 : y + 1) * L.ys;
     if constexpr (D == 3) {
-      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-      const int zz[3] = {zm, z, zp};
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) rows[b][c] = (uint32_t(zz[c]) * uint32_t(ny) + uint32_t(yy[b])) * uint32_t(nx);
+      zoff[0] = uint64_t(z == 0 ? nz - 1 : z - 1) * L.zs;
+      zoff[1] = uint64_t(z) * L.zs;
+      zoff[2] = uint64_t(z == nz - 1 ? 0 : z + 1) * L.zs;
     } else {
-#pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const uint32_t r = (uint32_t(z) * uint32_t(ny) + uint32_t(yy[b])) * uint32_t(nx);
-        rows[b][0] = r;
-        rows[b][1] = r;
-        rows[b][2] = r;
-      }
+      zoff[0] = zoff[1] = zoff[2] = uint64_t(z) * L.zs;
     }
   }
-  // cell at x + s * xi (s = -1 or +1) for velocity (cx, cy, cz)
-  __device__ __forceinline__ uint32_t at(int cx, int cy, int cz, int s) const {
-    return rows[1 + s * cy][1 + s * cz] + xs[1 + s * cx];
-  }
+  // element offset (without the population term) of the cell at x + s * xi
+  __device__ __forceinline__ uint64_t zpart(int cz, int s) const { return zoff[1 + s * cz]; }
+  __device__ __forceinline__ uint32_t lane(int cx, int cy, int s) const { return yoff[1 + s * cy] + xs[1 + s * cx]; }
 };
 
+template <class ST>
+__device__ __forceinline__ ST ldp(const ST *base, uint64_t uniform, uint32_t lane) {
+  return (base + uniform)[lane];
+}
+template <class ST>
+__device__ __forceinline__ void stp(ST *base, uint64_t uniform, uint32_t lane, ST v) {
+  __builtin_nontemporal_store(v, (base + uniform) + lane);
+}
+
+// natural-index helpers for the batched kernel (cell = (z * ny + y) * nx + x inside a box)
 template <class ST>
 __device__ __forceinline__ ST ld(const ST *base, uint32_t plane, int i, uint32_t cell) {
   return base[size_t(i) * plane + cell];
 }
 template <class ST>
 __device__ __forceinline__ void st(ST *base, uint32_t plane, int i, uint32_t cell, ST v) {
-  base[size_t(i) * plane + cell] = v;
+  __builtin_nontemporal_store(v, base + size_t(i) * plane + cell);
 }
+
+template <int D>
+struct NbrNat {
+  uint32_t rows[3][3];
+  uint32_t xs[3];
+  __device__ __forceinline__ NbrNat(int x, int y, int z, int nx, int ny, int nz) {
+    xs[0] = uint32_t(x == 0 ? nx - 1 : x - 1);
+    xs[1] = uint32_t(x);
+    xs[2] = uint32_t(x == nx - 1 ? 0 : x + 1);
+    const int yy[3] = {y == 0 ? ny - 1 : y - 1, y, y == ny - 1 ? 0 : y + 1};
+    const int zz[3] = {D == 3 ? (z == 0 ? nz - 1 : z - 1) : z, z, D == 3 ? (z == nz - 1 ? 0 : z + 1) : z};
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rows[b][c] = (uint32_t(zz[c]) * uint32_t(ny) + uint32_t(yy[b])) * uint32_t(nx);
+  }
+  __device__ __forceinline__ uint32_t at(int cx, int cy, int cz, int s) const {
+    return rows[1 + s * cy][1 + s * cz] + xs[1 + s * cx];
+  }
+};
 
 // ---------------------------------------------------------------------------------------
 // fused stream + collide
@@ -114,8 +151,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
   using L = Lat<S>;
   const CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, a.swizzle);
   if (!p.valid) return;
-  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz);
-  const uint32_t self = nb.rows[1][1] + uint32_t(p.x);
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
 
   CT g[L::G];
   sfor<L::G>([&](auto E) { g[E] = CT(0); });
@@ -123,11 +159,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     if constexpr (PAT == PULL) {
-      g[L::gidx(i)] = CT(ld(a.src, a.plane, i, nb.at(cx, cy, cz, -1)));
+      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     } else if constexpr (PAT == AA_EVEN) {
-      g[L::gidx(i)] = CT(ld(a.src, a.plane, i, self));
+      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1)));
     } else {
-      g[L::gidx(i)] = CT(ld(a.src, a.plane, L::opp(i), nb.at(cx, cy, cz, -1)));
+      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(L::opp(i)) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     }
   });
 
@@ -138,11 +174,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     const ST v = ST(g[L::gidx(i)]);
     if constexpr (PAT == PULL) {
-      st(a.dst, a.plane, i, self, v);
+      stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else if constexpr (PAT == AA_EVEN) {
-      st(a.dst, a.plane, L::opp(i), self, v);
+      stp(a.dst, uint64_t(L::opp(i)) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else {
-      st(a.dst, a.plane, i, nb.at(cx, cy, cz, +1), v);
+      stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
     }
   });
 }
@@ -151,8 +187,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
 // readers / writers of the canonical state
 // ---------------------------------------------------------------------------------------
 struct FieldArgs {
-  void *buf;          // population buffer (storage type), first cell of the box
-  uint32_t plane;     // population plane stride of the buffer in elements
+  void *buf;          // population buffer (storage type), first element of the box
+  Strides L;          // storage layout of the buffer
   uint32_t ncells;    // cells of the box (stride of the FP64 field arrays)
   int nx, ny, nz;
   int tiles_x, tiles_y;
@@ -166,34 +202,37 @@ struct FieldArgs {
   int i0, i1;             // population range of export / import (chunking)
 };
 
-// address of the canonical df_i(x) in the buffer for layout GM
+// storage address (uniform part, lane part) of the canonical df_i(x) for layout GM
 template <int S, int GM>
-__device__ __forceinline__ void canon_addr(const Nbr<Lat<S>::D> &nb, uint32_t self, int i, int cx, int cy, int cz,
-                                           int &slot, uint32_t &cell) {
+__device__ __forceinline__ void canon_addr(const Nbr<Lat<S>::D> &nb, const Strides &L, int i, int cx, int cy,
+                                           int cz, uint64_t &uni, uint32_t &lane) {
   if constexpr (GM == G_NATURAL) {
-    slot = i;
-    cell = self;
+    uni = uint64_t(i) * L.ps + nb.zpart(0, 1);
+    lane = nb.lane(0, 0, 1);
   } else if constexpr (GM == G_SHIFTED) {
-    slot = i;
-    cell = nb.at(cx, cy, cz, -1);
+    uni = uint64_t(i) * L.ps + nb.zpart(cz, -1);
+    lane = nb.lane(cx, cy, -1);
   } else {
-    slot = Lat<S>::opp(i);
-    cell = nb.at(cx, cy, cz, -1);
+    uni = uint64_t(Lat<S>::opp(i)) * L.ps + nb.zpart(cz, -1);
+    lane = nb.lane(cx, cy, -1);
   }
+}
+
+__device__ __forceinline__ uint32_t nat_cell(const FieldArgs &a, const CellPos &p) {
+  return (uint32_t(p.z) * uint32_t(a.ny) + uint32_t(p.y)) * uint32_t(a.nx) + uint32_t(p.x);
 }
 
 template <int S, int GM, class ST>
 __device__ __forceinline__ void gather_canon(const FieldArgs &a, const CellPos &p, double *f) {
   using L = Lat<S>;
-  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz);
-  const uint32_t self = nb.rows[1][1] + uint32_t(p.x);
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
   const ST *buf = static_cast<const ST *>(a.buf);
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    int slot;
-    uint32_t cell;
-    canon_addr<S, GM>(nb, self, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), slot, cell);
-    f[i] = double(ld(buf, a.plane, slot, cell));
+    uint64_t uni;
+    uint32_t lane;
+    canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
+    f[i] = double(ldp(buf, uni, lane));
   });
 }
 
@@ -203,8 +242,8 @@ __global__ void __launch_bounds__(256) init_kernel(FieldArgs a) {
   using L = Lat<S>;
   const CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, 0);
   if (!p.valid) return;
-  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz);
-  const uint32_t self = nb.rows[1][1] + uint32_t(p.x);
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
+  const uint32_t self = nat_cell(a, p);
   const double drho = a.rho_in[self] - 1.0;
   double u[3] = {a.u_in[self], a.u_in[size_t(a.ncells) + self], L::D == 3 ? a.u_in[2 * size_t(a.ncells) + self] : 0.0};
   double g[L::G];
@@ -212,10 +251,10 @@ __global__ void __launch_bounds__(256) init_kernel(FieldArgs a) {
   ST *buf = static_cast<ST *>(a.buf);
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
-    int slot;
-    uint32_t cell;
-    canon_addr<S, GM>(nb, self, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), slot, cell);
-    st(buf, a.plane, slot, cell, ST(g[L::gidx(i)]));
+    uint64_t uni;
+    uint32_t lane;
+    canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
+    stp(buf, uni, lane, ST(g[L::gidx(i)]));
   });
 }
 
@@ -224,16 +263,16 @@ __global__ void __launch_bounds__(256) export_kernel(FieldArgs a) {
   using L = Lat<S>;
   const CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, 0);
   if (!p.valid) return;
-  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz);
-  const uint32_t self = nb.rows[1][1] + uint32_t(p.x);
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
+  const uint32_t self = nat_cell(a, p);
   const ST *buf = static_cast<const ST *>(a.buf);
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if (i >= a.i0 && i < a.i1) {
-      int slot;
-      uint32_t cell;
-      canon_addr<S, GM>(nb, self, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), slot, cell);
-      a.pop[size_t(i - a.i0) * a.ncells + self] = double(ld(buf, a.plane, slot, cell));
+      uint64_t uni;
+      uint32_t lane;
+      canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
+      a.pop[size_t(i - a.i0) * a.ncells + self] = double(ldp(buf, uni, lane));
     }
   });
 }
@@ -243,16 +282,16 @@ __global__ void __launch_bounds__(256) import_kernel(FieldArgs a) {
   using L = Lat<S>;
   const CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, 0);
   if (!p.valid) return;
-  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz);
-  const uint32_t self = nb.rows[1][1] + uint32_t(p.x);
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
+  const uint32_t self = nat_cell(a, p);
   ST *buf = static_cast<ST *>(a.buf);
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     if (i >= a.i0 && i < a.i1) {
-      int slot;
-      uint32_t cell;
-      canon_addr<S, GM>(nb, self, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), slot, cell);
-      st(buf, a.plane, slot, cell, ST(a.pop[size_t(i - a.i0) * a.ncells + self]));
+      uint64_t uni;
+      uint32_t lane;
+      canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
+      stp(buf, uni, lane, ST(a.pop[size_t(i - a.i0) * a.ncells + self]));
     }
   });
 }
@@ -273,7 +312,7 @@ __global__ void __launch_bounds__(256) macro_kernel(FieldArgs a) {
     if constexpr (L::c(i, 2) != 0) j[2] += double(L::c(i, 2)) * f[i];
   });
   const double rho = 1.0 + drho;
-  const uint32_t self = (uint32_t(p.z) * uint32_t(a.ny) + uint32_t(p.y)) * uint32_t(a.nx) + uint32_t(p.x);
+  const uint32_t self = nat_cell(a, p);
   a.rho_out[self] = rho;
   a.u_out[self] = j[0] / rho;
   a.u_out[size_t(a.ncells) + self] = j[1] / rho;

@@ -23,18 +23,42 @@ int stencil_q(int s) { return s == LBM_D2Q9 ? 9 : (s == LBM_D3Q19 ? 19 : 27); }
 int stencil_d(int s) { return s == LBM_D2Q9 ? 2 : 3; }
 size_t storage_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
 
-// Population plane stride in elements: ncells plus a padding that staggers the start of the
-// q planes across HBM channels (a power-of-two plane size puts all q streams of a cell on
-// the same channel offset).  LBM_PLANE_PAD_BYTES overrides the default padding.
+// Population plane stride in elements for the PLANES layout: ncells rounded up to 256 bytes
+// plus a padding that staggers the start of the q planes across HBM channels (a power-of-two
+// plane size puts the q streams of a cell at the same channel offset).  LBM_PLANE_PAD_BYTES
+// overrides the default padding.
 size_t plane_elems(const lbm_params *p) {
   const size_t ncells = size_t(p->nx) * size_t(p->ny) * size_t(p->nz);
   const size_t eb = storage_bytes(p->storage);
   size_t pad_bytes = kDefaultPlanePadBytes;
   if (const char *env = std::getenv("LBM_PLANE_PAD_BYTES")) pad_bytes = size_t(std::strtoull(env, nullptr, 10));
-  // keep every plane 256-byte aligned
   const size_t align = 256 / eb;
   const size_t base = (ncells + align - 1) / align * align;
   return base + (pad_bytes / 256) * align;
+}
+
+int resolve_layout(const lbm_params *p) {
+  if (p->layout == LBM_LAYOUT_PLANES || p->layout == LBM_LAYOUT_ROWS) return p->layout;
+  return p->storage == LBM_STORE_F64 ? LBM_LAYOUT_PLANES : LBM_LAYOUT_ROWS;
+}
+
+// element strides of population i, z and y (x has stride 1) and elements per buffer
+void storage_strides(const lbm_params *p, uint64_t *ps, uint64_t *zs, uint64_t *ys, uint64_t *elems) {
+  const uint64_t nx = uint64_t(p->nx), ny = uint64_t(p->ny), nz = uint64_t(p->nz);
+  const uint64_t q = uint64_t(stencil_q(p->stencil));
+  if (resolve_layout(p) == LBM_LAYOUT_PLANES) {
+    *ps = plane_elems(p);
+    *ys = nx;
+    *zs = ny * nx;
+    *elems = q * *ps;
+  } else {
+    const uint64_t align = 256 / storage_bytes(p->storage);
+    const uint64_t nxp = (nx + align - 1) / align * align;
+    *ps = nxp;
+    *ys = q * nxp;
+    *zs = ny * *ys;
+    *elems = nz * *zs;
+  }
 }
 
 int resolve_eq_form(const lbm_params *p) {
@@ -240,8 +264,13 @@ lbm_status validate(const lbm_params *p) {
   if (!p->periodic[0] || !p->periodic[1] || !p->periodic[2])
     return fail(LBM_EUNSUPPORTED, "only periodic boundaries are implemented");
   const double ncells = double(p->nx) * double(p->ny) * double(p->nz);
-  if (double(plane_elems(p)) * double(storage_bytes(p->storage)) >= 4294967296.0)
-    return fail(LBM_EUNSUPPORTED, "one population plane must stay below 4 GiB (32-bit offsets)");
+  if (p->layout < LBM_LAYOUT_AUTO || p->layout > LBM_LAYOUT_ROWS) return fail(LBM_EINVAL, "layout out of range");
+  {
+    uint64_t ps, zs, ys, elems;
+    storage_strides(p, &ps, &zs, &ys, &elems);
+    if (double(zs) >= 4294967295.0)
+      return fail(LBM_EUNSUPPORTED, "one z-plane of the population storage must stay below 2^32 elements");
+  }
   if (p->nx > 2147483647 || p->ny > 2147483647 || p->nz > 2147483647) return fail(LBM_EINVAL, "dims too large");
   return LBM_OK;
 }
@@ -277,7 +306,9 @@ extern "C" lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes) {
   if (s != LBM_OK) return s;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
   const size_t nbuf = p->streaming == LBM_STREAM_PULL ? 2 : 1;
-  *bytes = nbuf * size_t(stencil_q(p->stencil)) * plane_elems(p) * storage_bytes(p->storage);
+  uint64_t ps, zs, ys, elems;
+  storage_strides(p, &ps, &zs, &ys, &elems);
+  *bytes = nbuf * size_t(elems) * storage_bytes(p->storage);
   return LBM_OK;
 }
 

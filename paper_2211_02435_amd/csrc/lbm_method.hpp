@@ -1,6 +1,8 @@
 // Host-side method description shared by the library's translation units.
 #pragma once
 
+#include <stdint.h>
+
 #include <string>
 
 #include "../../include/lbm.h"
@@ -24,6 +26,8 @@ int stencil_d(int s);
 size_t storage_bytes(int st);
 int resolve_eq_form(const lbm_params *p);
 size_t plane_elems(const lbm_params *p);
+int resolve_layout(const lbm_params *p);
+void storage_strides(const lbm_params *p, uint64_t *ps, uint64_t *zs, uint64_t *ys, uint64_t *elems);
 constexpr size_t kDefaultPlanePadBytes = 0;
 lbm_status validate(const lbm_params *p);
 lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out);

@@ -98,14 +98,15 @@ struct lbm_ctx {
   int s = 0, q = 0, d = 0, space = 0, eq = 0, store = 0, pattern = 0;
   int nx = 1, ny = 1, nz = 1;
   uint32_t ncells = 0;
-  uint32_t plane = 0;   // population plane stride (elements), >= ncells
+  Strides L{};          // storage layout strides (elements)
+  int layout = 0;
   size_t elem = 4;
   RelaxHost R{};
   bool reg = false;
   void *buf[2] = {nullptr, nullptr};
   bool own[2] = {false, false};
   int nbuf = 2;
-  size_t plane_bytes = 0, buf_bytes = 0;
+  size_t buf_bytes = 0;
   int cur = 0;        // pull: buffer holding the state
   int64_t t = 0;      // steps since init
   hipStream_t stream = nullptr;
@@ -130,7 +131,7 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.nx = c->nx;
   a.ny = c->ny;
   a.nz = c->nz;
-  a.plane = c->plane;
+  a.L = c->L;
   a.tiles_x = (c->nx + c->bx - 1) / c->bx;
   a.tiles_y = (c->ny + c->by - 1) / c->by;
   a.swizzle = c->swz;
@@ -202,7 +203,7 @@ static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
   FieldArgs a;
   std::memset(&a, 0, sizeof(a));
   a.buf = buf;
-  a.plane = c->plane;
+  a.L = c->L;
   a.ncells = c->ncells;
   a.nx = c->nx;
   a.ny = c->ny;
@@ -283,9 +284,15 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   }
   c->reg = c->R.regularized;
   c->nbuf = c->pattern == LBM_STREAM_PULL ? 2 : 1;
-  c->plane = uint32_t(plane_elems(p));
-  c->plane_bytes = size_t(c->plane) * c->elem;
-  c->buf_bytes = c->plane_bytes * size_t(c->q);
+  {
+    uint64_t ps, zs, ys, elems;
+    storage_strides(p, &ps, &zs, &ys, &elems);
+    c->L.ps = ps;
+    c->L.zs = zs;
+    c->L.ys = uint32_t(ys);
+    c->layout = resolve_layout(p);
+    c->buf_bytes = size_t(elems) * c->elem;
+  }
   for (int k = 0; k < c->nbuf; ++k) {
     if (p->buffers[k]) {
       if (p->buffer_bytes < c->buf_bytes) {
@@ -866,7 +873,9 @@ static FieldArgs batch_field(const lbm_batch *b, int k, void *base) {
   FieldArgs a;
   std::memset(&a, 0, sizeof(a));
   a.buf = static_cast<char *>(base) + size_t(B.off) * b->elem;
-  a.plane = b->ntot;
+  a.L.ps = b->ntot;
+  a.L.zs = uint64_t(B.nx) * uint64_t(B.ny);
+  a.L.ys = uint32_t(B.nx);
   a.ncells = B.ncells;
   a.nx = B.nx;
   a.ny = B.ny;

@@ -20,6 +20,7 @@ EQUILIBRIA = {"maxwellian": 0, "swe": 1}
 EQ_FORMS = {"default": 0, "absolute": 1, "delta": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 STREAMING = {"pull": 0, "aa": 1}
+LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
@@ -29,7 +30,8 @@ class LbmParams(ctypes.Structure):
                 ("zero_centered", c_int), ("omegas", POINTER(c_double)), ("n_omegas", c_int),
                 ("gravity", c_double), ("nx", c_int64), ("ny", c_int64), ("nz", c_int64),
                 ("periodic", c_int * 3), ("storage", c_int), ("streaming", c_int),
-                ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p)]
+                ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p),
+                ("layout", c_int)]
 
 
 class LbmError(RuntimeError):
@@ -114,7 +116,7 @@ def _dptr(a):
 
 
 def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", equilibrium="maxwellian",
-                eq_form="default", gravity=0.0, zero_centered=1):
+                eq_form="default", gravity=0.0, zero_centered=1, layout="auto"):
     p = LbmParams()
     check(load().lbm_params_default(ctypes.byref(p)))
     p.stencil = STENCILS[stencil]
@@ -130,6 +132,7 @@ def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", e
     p.nx, p.ny, p.nz = (int(v) for v in dims)
     p.storage = STORAGE[storage]
     p.streaming = STREAMING[streaming]
+    p.layout = LAYOUTS[layout]
     return p
 
 
@@ -150,14 +153,15 @@ class Lattice:
     (torch_buffers=True) or by the library.  Work runs on a torch stream of default priority."""
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
-                 equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True):
+                 equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto"):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
         self.q = Q[stencil]
         self.dims = tuple(int(v) for v in dims)
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
-        p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity)
+        p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
+                        layout=layout)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []

@@ -73,11 +73,24 @@ def test_valid_parameter_sets():
     (dict(stencil="D2Q9", dims=(8, 8, 2)), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D3Q27", space="central", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D2Q9", space="cumulant", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
-    (dict(dims=(2048, 2048, 256), storage="f32"), lbm.LBM_EUNSUPPORTED),
+    (dict(dims=(65536, 4096, 2), storage="f32", layout="rows"), lbm.LBM_EUNSUPPORTED),
+    (dict(layout="diagonal"), None),
 ])
 def test_invalid_parameter_sets(kw, code):
+    if code is None:  # an unknown layout name never reaches the library
+        with pytest.raises(KeyError):
+            _p(**kw)
+        return
     assert lbm.lbm_validate(_p(**kw)) == code
     assert lbm.last_error() != ""
+
+
+def test_layout_enum_checked_and_large_boxes_accepted():
+    p = _p()
+    p.layout = 7
+    assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+    # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
+    assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
 
 
 def test_nonperiodic_rejected():

@@ -68,13 +68,14 @@ def test_init_equilibrium_matches_oracle(stencil, space, streaming):
                                            ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
                                            ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")])
 @pytest.mark.parametrize("kind", ["reg", "gen"])
-def test_sweep_fp64_matches_oracle(stencil, space, kind):
+@pytest.mark.parametrize("layout", ["planes", "rows"])
+def test_sweep_fp64_matches_oracle(stencil, space, kind, layout):
     """Non-equilibrium start (equilibrium + noise from the oracle), 4 steps, FP64."""
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     om = _rates(stencil, kind, seed=3)
     m = O.Method(stencil, space, om)
     df0 = _noisy_state(m, dims, seed=11)
-    lat = _lattice(stencil, space, om, dims, storage="f64")
+    lat = _lattice(stencil, space, om, dims, storage="f64", layout=layout)
     lat.lbm_set_populations(df0)
     lat.lbm_step(4)
     got = lat.lbm_get_populations()
@@ -133,13 +134,15 @@ def test_config_d2q9_central_64_taylor_green():
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
 @pytest.mark.parametrize("n", [1, 2, 5])
-def test_streaming_index_maps_bit_exact(stencil, streaming, n):
+@pytest.mark.parametrize("layout", ["planes", "rows"])
+def test_streaming_index_maps_bit_exact(stencil, streaming, n, layout):
     """Identity collision: n steps of streaming equal numpy.roll bit for bit."""
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     q = O.stencil(stencil).q
     rng = np.random.default_rng(7)
     df = rng.integers(-1000, 1000, size=(q, dims[2], dims[1], dims[0])).astype(np.float64) / 1024.0
-    lat = _lattice(stencil, "raw", _rates(stencil, "reg"), dims, storage="f32", streaming=streaming)
+    lat = _lattice(stencil, "raw", _rates(stencil, "reg"), dims, storage="f32", streaming=streaming,
+                   layout=layout)
     lat.lbm_set_populations(df)
     lat.lbm_debug_stream_only(n)
     got = lat.lbm_get_populations()
@@ -150,19 +153,22 @@ def test_streaming_index_maps_bit_exact(stencil, streaming, n):
     np.testing.assert_array_equal(got, want)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("n", [3, 4])
-def test_aa_equals_pull(storage, n):
+def test_aa_equals_pull_in_both_layouts(storage, n):
+    """Pull and AA, planes and rows: four kernels sharing one collision, bit-equal results."""
     dims = RAGGED3
     om = _rates("D3Q27", "reg")
     rho, u = W.tgv3d_fields(*dims, u0=0.05, period=16)
     outs = []
     for streaming in ("pull", "aa"):
-        lat = _lattice("D3Q27", "cumulant", om, dims, storage=storage, streaming=streaming)
-        lat.lbm_init_equilibrium(rho, u)
-        lat.lbm_step(n)
-        outs.append(lat.lbm_get_populations())
-    np.testing.assert_array_equal(outs[0], outs[1])
+        for layout in ("planes", "rows"):
+            lat = _lattice("D3Q27", "cumulant", om, dims, storage=storage, streaming=streaming, layout=layout)
+            lat.lbm_init_equilibrium(rho, u)
+            lat.lbm_step(n)
+            outs.append(lat.lbm_get_populations())
+    for o in outs[1:]:
+        np.testing.assert_array_equal(outs[0], o)
 
 
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
