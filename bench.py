@@ -12,7 +12,6 @@ the FP32-vs-FP64 velocity difference and the FP64 CPU oracle timed on a bounded 
   python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload d3q27_cumulant_512]
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -28,15 +27,6 @@ import lbm_workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
-KERNEL_SOURCES = ["paper_2211_02435_amd/csrc/lbm_device.hpp", "paper_2211_02435_amd/csrc/lbm_kernels.hpp"]
-
-
-def kernel_source_hash():
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload, lups_per_launch):
@@ -47,6 +37,7 @@ def measured_traffic(workload, lups_per_launch):
         return None
     with open(path) as f:
         t = json.load(f)
+    from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
@@ -145,7 +136,7 @@ def main():
     bytes32 = 2 * q * 4 * cells
     t_launch32 = ev32 / 1e3 / args.steps
     achieved32 = bytes32 / t_launch32 / 1e9
-    launch32 = lat32.lbm_get_launch()
+    launch32 = list(lat32.lbm_get_launch()) + [int(lat32.lbm_get_vectorized())]
     print("[bench] fp32 done: %.0f MLUPS, %.1f GB/s" % (mlups32, achieved32), file=sys.stderr, flush=True)
 
     result_fp64 = None
@@ -158,7 +149,7 @@ def main():
                        "ms_per_step": wall64 * 1e3 / args.steps,
                        "achieved_GBps": 2 * q * 8 * cells / t_launch64 / 1e9,
                        "frac": 2 * q * 8 * cells / t_launch64 / 1e9 / HBM_PEAK_GBS,
-                       "launch": lat64.lbm_get_launch()}
+                       "launch": list(lat64.lbm_get_launch()) + [int(lat64.lbm_get_vectorized())]}
         _, u32 = velocity_device(lat32, lbm)
         _, u64 = velocity_device(lat64, lbm)
         vel_err = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
@@ -196,7 +187,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic Taylor-Green vortex initial fields",
         "config": {"workload": workload, "cells": cells, "stencil": stencil, "space": space,
-                   "storage": "f32", "streaming": args.streaming, "layout": args.layout, "launch": launch32},
+                   "storage": "f32", "streaming": args.streaming,
+                   "layout": args.layout if args.layout != "auto" else "planes (auto for f32)",
+                   "launch_bx_by_swizzle_vec": launch32},
         "roofline": {"bound": "hbm", "achieved": achieved32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved32 / HBM_PEAK_GBS,
                      "traffic": measured_traffic(args.workload if n == cfg["dims"][0] else "none", cells),

@@ -92,8 +92,8 @@ typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1 } lbm_streaming;
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
- * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS for F32 and
- * F16 storage, PLANES for F64 (the faster layout measured for each on MI355X). */
+ * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: PLANES for F32 and
+ * F16 storage, ROWS for F64 (the faster layout measured for each on MI355X). */
 typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 } lbm_layout;
 
 typedef struct {
@@ -183,9 +183,18 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
 lbm_status lbm_set_launch(lbm_ctx *ctx, int bx, int by, int xcd_swizzle);
 lbm_status lbm_get_launch(const lbm_ctx *ctx, int *bx, int *by, int *xcd_swizzle);
 
-/* Time candidate launch shapes on the context's own buffers (state is left unchanged) and
- * keep the fastest; results are cached per (method, precision, pattern, size) in the JSON
- * file named by LBM_AUTOTUNE_CACHE, if set. */
+/* Vectorised sweep: each lane owns V x-adjacent cells (V = 2 for F64/F32, 4 for F16) and reads
+ * each population row segment with one aligned vector load, the x +- 1 neighbours coming from
+ * the adjacent lane (wave shift).  Needs nx to be a multiple of bx * V (LBM_EUNSUPPORTED
+ * otherwise); AA odd steps always use the per-cell kernel.  Off by default; lbm_autotune
+ * considers it. */
+lbm_status lbm_set_vectorized(lbm_ctx *ctx, int enable);
+int lbm_get_vectorized(const lbm_ctx *ctx);
+
+/* Time candidate launch shapes (block shape, XCD swizzle, vectorised or per-cell kernel) on
+ * the context's own buffers (state is left unchanged) and keep the fastest; results are
+ * cached per (method, precision, pattern, layout, size) in the JSON file named by
+ * LBM_AUTOTUNE_CACHE, if set. */
 lbm_status lbm_autotune(lbm_ctx *ctx);
 
 /* Enable (1) or disable (0) hipGraph recording in lbm_step. */

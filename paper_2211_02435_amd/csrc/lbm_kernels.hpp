@@ -184,6 +184,103 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// vectorised sweep: V x-adjacent cells per lane (V = 2 for FP32 and FP64, 4 for FP16: 8- or
+// 16-byte accesses; wider FP32 vectors cost more registers than they gain in bandwidth)
+// Requires nx % (blockDim.x * V) == 0, so every wave covers 64 V consecutive cells of one row.
+// Each population row segment is read with one aligned vector load; the x - 1 and x + 1
+// neighbours of the first and last cell come from the adjacent lane through a wave shift
+// (DPP), and lanes 0 and 63 fetch the cell beyond their wave with one wrapped scalar load.
+// ---------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp(int(b), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(int(b >> 32), CTRL, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, (long long)(unsigned(lo)) | ((long long)hi << 32));
+}
+constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l receives lane l - 1
+constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l receives lane l + 1
+
+template <class ST, int V> struct VecOf;
+template <> struct VecOf<float, 2> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<double, 2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<_Float16, 4> { typedef _Float16 T __attribute__((ext_vector_type(4))); };
+
+template <class ST> struct VecWidth { static constexpr int V = sizeof(ST) == 2 ? 4 : 2; };
+
+template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT>
+__global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
+  using L = Lat<S>;
+  constexpr int V = VecWidth<ST>::V;
+  using VT = typename VecOf<ST, V>::T;
+  static_assert(PAT == PULL || PAT == AA_EVEN, "vectorised sweep: pull and AA even steps");
+  uint32_t tile = blockIdx.x;
+  if (a.swizzle) tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t per_plane = uint32_t(a.tiles_x) * uint32_t(a.tiles_y);
+  const uint32_t tz = tile / per_plane;
+  const uint32_t r = tile - tz * per_plane;
+  const uint32_t ty = r / uint32_t(a.tiles_x);
+  const uint32_t tx = r - ty * uint32_t(a.tiles_x);
+  const int x0 = int((tx * blockDim.x + threadIdx.x) * V);
+  const int y = int(ty * blockDim.y + threadIdx.y);
+  const int z = int(tz);
+  if (y >= a.ny) return;  // whole waves (blockDim.x is a multiple of 64)
+  const Nbr<L::D> nb(x0, y, z, a.nx, a.ny, a.nz, a.L);
+  const uint32_t lane_id = threadIdx.x & 63u;
+  const uint32_t xw_lo = uint32_t(x0 == 0 ? a.nx - 1 : x0 - 1);       // cell before this lane
+  const uint32_t xw_hi = uint32_t(x0 + V == a.nx ? 0 : x0 + V);       // cell after this lane
+
+  CT g[V][L::G];
+  sfor<V>([&](auto K) { sfor<L::G>([&](auto E) { g[K][E] = CT(0); }); });
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+    constexpr int gi = L::gidx(i);
+    uint64_t uni;
+    uint32_t row;
+    if constexpr (PAT == PULL) {
+      uni = uint64_t(i) * a.L.ps + nb.zpart(cz, -1);
+      row = nb.yoff[1 - cy];
+    } else {
+      uni = uint64_t(i) * a.L.ps + nb.zpart(0, 1);
+      row = nb.yoff[1];
+    }
+    const ST *rp = a.src + uni + row;
+    const VT w = *reinterpret_cast<const VT *>(rp + x0);
+    CT own[V];
+    sfor<V>([&](auto K) { constexpr int k = decltype(K)::value; own[k] = CT(w[k]); });
+    if constexpr (PAT == AA_EVEN || cx == 0) {
+      sfor<V>([&](auto K) { g[K][gi] = own[K]; });
+    } else if constexpr (cx == 1) {  // source x - 1
+      CT prev = dpp_mov<DPP_WAVE_SHR1>(own[V - 1]);
+      if (lane_id == 0) prev = CT(rp[xw_lo]);
+      g[0][gi] = prev;
+      sfor<V - 1>([&](auto K) { g[K + 1][gi] = own[K]; });
+    } else {  // source x + 1
+      CT next = dpp_mov<DPP_WAVE_SHL1>(own[0]);
+      if (lane_id == 63) next = CT(rp[xw_hi]);
+      sfor<V - 1>([&](auto K) { g[K][gi] = own[K + 1]; });
+      g[V - 1][gi] = next;
+    }
+  });
+
+  sfor<V>([&](auto K) { collide<S, SP, EQ, REG, CT>(g[K], a.R, a.grav); });
+
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int slot = PAT == PULL ? i : L::opp(i);
+    VT o;
+    sfor<V>([&](auto K) { constexpr int k = decltype(K)::value; o[k] = ST(g[k][L::gidx(i)]); });
+    ST *dp = a.dst + (uint64_t(slot) * a.L.ps + nb.zpart(0, 1)) + nb.yoff[1];
+    __builtin_nontemporal_store(o, reinterpret_cast<VT *>(dp + x0));
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // readers / writers of the canonical state
 // ---------------------------------------------------------------------------------------
 struct FieldArgs {

@@ -39,6 +39,7 @@ namespace lbm {
   return nullptr;
 
 const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweep, sp, eq, reg, pat) }
+const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -60,9 +61,12 @@ __global__ void __launch_bounds__(DIAG_THREADS) diag_final_kernel(const double *
   if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
-// plain 16-byte copy: the practical HBM ceiling
-__global__ void __launch_bounds__(256) copy_kernel(uint4 *__restrict__ dst, const uint4 *__restrict__ src, size_t n) {
-  for (size_t i = size_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += size_t(gridDim.x) * 256) dst[i] = src[i];
+// plain copy, one 16-byte vector per lane and one lane per vector: the practical HBM ceiling
+// (the fastest of the copy forms measured on MI355X; grid-stride and unrolled forms were slower)
+typedef unsigned int lbm_v4u __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) copy_kernel(lbm_v4u *__restrict__ dst, const lbm_v4u *__restrict__ src, size_t n) {
+  const size_t i = size_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i < n) __builtin_nontemporal_store(src[i], dst + i);
 }
 
 const void *diag_final_fn() { return reinterpret_cast<const void *>(&diag_final_kernel); }
@@ -112,6 +116,7 @@ struct lbm_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   int bx = 64, by = 4, swz = 0;
+  bool vec = false;   // vectorised sweep (V cells per lane) where the shape allows it
   bool graphs = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
@@ -122,8 +127,12 @@ struct lbm_ctx {
 
 namespace lbm {
 
+static int vec_width(int store) { return store == F16 ? 4 : 2; }
+// the vectorised kernel runs when every wave covers whole 64 V-cell chunks of one row
+static bool vec_ok(const lbm_ctx *c, int bx) { return bx % 64 == 0 && c->nx % (bx * vec_width(c->store)) == 0; }
+
 template <class ST, class CT>
-static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void *dst) {
+static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void *dst, bool vec) {
   SweepArgs<ST, CT> a;
   std::memset(&a, 0, sizeof(a));
   a.src = static_cast<const ST *>(src);
@@ -132,7 +141,8 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.ny = c->ny;
   a.nz = c->nz;
   a.L = c->L;
-  a.tiles_x = (c->nx + c->bx - 1) / c->bx;
+  const int cells_x = c->bx * (vec ? vec_width(c->store) : 1);
+  a.tiles_x = (c->nx + cells_x - 1) / cells_x;
   a.tiles_y = (c->ny + c->by - 1) / c->by;
   a.swizzle = c->swz;
   a.grav = CT(c->p.gravity);
@@ -148,23 +158,19 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   return a;
 }
 
-static dim3 sweep_grid(const lbm_ctx *c) {
-  const uint64_t tx = (c->nx + c->bx - 1) / c->bx, ty = (c->ny + c->by - 1) / c->by;
-  return dim3(unsigned(tx * ty * uint64_t(c->nz)));
-}
-
 template <class ST, class CT>
-static hipError_t launch_sweep_t(const lbm_ctx *c, const void *fn, const void *src, void *dst) {
-  SweepArgs<ST, CT> a = make_sweep_args<ST, CT>(c, src, dst);
+static hipError_t launch_sweep_t(const lbm_ctx *c, const void *fn, const void *src, void *dst, bool vec) {
+  SweepArgs<ST, CT> a = make_sweep_args<ST, CT>(c, src, dst, vec);
   void *args[] = {&a};
-  return hipLaunchKernel(fn, sweep_grid(c), dim3(c->bx, c->by), args, 0, c->stream);
+  const dim3 grid(unsigned(uint64_t(a.tiles_x) * uint64_t(a.tiles_y) * uint64_t(c->nz)));
+  return hipLaunchKernel(fn, grid, dim3(c->bx, c->by), args, 0, c->stream);
 }
 
-static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src, void *dst) {
+static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src, void *dst, bool vec) {
   switch (c->store) {
-    case F64: return launch_sweep_t<double, double>(c, fn, src, dst);
-    case F32: return launch_sweep_t<float, float>(c, fn, src, dst);
-    default: return launch_sweep_t<_Float16, float>(c, fn, src, dst);
+    case F64: return launch_sweep_t<double, double>(c, fn, src, dst, vec);
+    case F32: return launch_sweep_t<float, float>(c, fn, src, dst, vec);
+    default: return launch_sweep_t<_Float16, float>(c, fn, src, dst, vec);
   }
 }
 
@@ -185,9 +191,10 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     src = c->buf[0];
     dst = c->buf[0];
   }
-  const void *fn = sweep_fn(c->s, c->store, sp, eq, reg, pat);
+  const bool vec = c->vec && pat != AA_ODD && vec_ok(c, c->bx);
+  const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);
   if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
-  HIPCHECK(launch_sweep(c, fn, src, dst), "sweep launch");
+  HIPCHECK(launch_sweep(c, fn, src, dst, vec), "sweep launch");
   if (c->pattern == LBM_STREAM_PULL) c->cur ^= 1;
   c->t += 1;
   return LBM_OK;
@@ -584,8 +591,20 @@ extern "C" lbm_status lbm_set_launch(lbm_ctx *c, int bx, int by, int swz) {
   c->bx = bx;
   c->by = by;
   c->swz = swz ? 1 : 0;
+  if (c->vec && !vec_ok(c, bx)) c->vec = false;
   return LBM_OK;
 }
+
+extern "C" lbm_status lbm_set_vectorized(lbm_ctx *c, int enable) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (enable && !vec_ok(c, c->bx))
+    return fail(LBM_EUNSUPPORTED, "the vectorised sweep needs nx to be a multiple of bx * V (V = 2 for F64/F32, 4 for F16)");
+  if (c->vec != (enable != 0)) clear_graphs(c);
+  c->vec = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_vectorized(const lbm_ctx *c) { return c && c->vec ? 1 : 0; }
 
 extern "C" lbm_status lbm_get_launch(const lbm_ctx *c, int *bx, int *by, int *swz) {
   if (!c || !bx || !by || !swz) return fail(LBM_EINVAL, "NULL argument");
@@ -633,11 +652,11 @@ extern "C" lbm_status lbm_time_steps(lbm_ctx *c, int64_t n, double *ms) {
 static std::string tune_key(const lbm_ctx *c) {
   std::ostringstream k;
   k << "s" << c->s << "_sp" << c->space << "_eq" << c->eq << "_r" << int(c->reg) << "_st" << c->store << "_pat"
-    << c->pattern << "_" << c->nx << "x" << c->ny << "x" << c->nz;
+    << c->pattern << "_lay" << c->layout << "_" << c->nx << "x" << c->ny << "x" << c->nz;
   return k.str();
 }
 
-static bool cache_lookup(const std::string &file, const std::string &key, int *bx, int *by, int *swz) {
+static bool cache_lookup(const std::string &file, const std::string &key, int *bx, int *by, int *swz, int *vec) {
   std::ifstream in(file);
   if (!in) return false;
   std::string line;
@@ -648,12 +667,13 @@ static bool cache_lookup(const std::string &file, const std::string &key, int *b
     size_t lb = line.find('[', p);
     if (lb == std::string::npos) continue;
     double ms = 0;
-    if (std::sscanf(line.c_str() + lb, "[%d, %d, %d, %lf", bx, by, swz, &ms) >= 3) return true;
+    if (std::sscanf(line.c_str() + lb, "[%d, %d, %d, %d, %lf", bx, by, swz, vec, &ms) >= 4) return true;
   }
   return false;
 }
 
-static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, double ms) {
+static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, int vec,
+                        double ms) {
   std::vector<std::string> lines;
   {
     std::ifstream in(file);
@@ -666,7 +686,7 @@ static void cache_store(const std::string &file, const std::string &key, int bx,
     }
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %.6f]", key.c_str(), bx, by, swz, ms);
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %.6f]", key.c_str(), bx, by, swz, vec, ms);
   lines.push_back(buf);
   std::ofstream out(file, std::ios::trunc);
   out << "{\n";
@@ -678,18 +698,23 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   const char *file = std::getenv("LBM_AUTOTUNE_CACHE");
   const std::string key = tune_key(c);
-  int bx, by, swz;
-  if (file && cache_lookup(file, key, &bx, &by, &swz)) return lbm_set_launch(c, bx, by, swz);
-  // candidate shapes
-  std::vector<std::array<int, 3>> cand;
+  int bx, by, swz, vec = 0;
+  if (file && cache_lookup(file, key, &bx, &by, &swz, &vec)) {
+    lbm_status s0 = lbm_set_launch(c, bx, by, swz);
+    return s0 != LBM_OK ? s0 : lbm_set_vectorized(c, vec);
+  }
+  // candidate shapes: (bx, by, swizzle, vectorised)
+  std::vector<std::array<int, 4>> cand;
   for (int cbx : {64, 128, 256, 512})
     for (int cby : {1, 2, 4, 8})
-      for (int cs : {0, 1}) {
-        if (cbx * cby > 512 || (cbx * cby) % 64 != 0) continue;
-        if (cbx > 64 && cbx / 2 >= c->nx) continue;
-        if (cby > 1 && cby / 2 >= c->ny) continue;
-        cand.push_back({cbx, cby, cs});
-      }
+      for (int cs : {0, 1})
+        for (int cv : {0, 1}) {
+          if (cbx * cby > 512 || (cbx * cby) % 64 != 0) continue;
+          if (cv && (cbx * cby > 256 || !vec_ok(c, cbx))) continue;
+          if (cbx > 64 && cbx / 2 >= c->nx) continue;
+          if (cby > 1 && cby / 2 >= c->ny) continue;
+          cand.push_back({cbx, cby, cs, cv});
+        }
   // the sweep must leave the state unchanged: pull writes only the other buffer; AA runs
   // on a copy of the buffer that is restored afterwards
   void *saved = nullptr;
@@ -704,12 +729,13 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   const int cur0 = c->cur;
   const int64_t t0 = c->t;
   const int bx0 = c->bx, by0 = c->by, swz0 = c->swz;
+  const bool vec0 = c->vec;
   const bool g0 = c->graphs;
   c->graphs = false;
   const uint64_t lups = uint64_t(c->ncells);
   const int reps = int(std::max<uint64_t>(2, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
   double best = 1e300;
-  int bb[3] = {bx0, by0, swz0};
+  int bb[4] = {bx0, by0, swz0, vec0 ? 1 : 0};
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0), "event");
   HIPCHECK(hipEventCreate(&e1), "event");
@@ -718,6 +744,7 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
     c->bx = cd[0];
     c->by = cd[1];
     c->swz = cd[2];
+    c->vec = cd[3] != 0;
     // warm-up, then time reps sweeps; pull: same src -> dst every time
     for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
       if (r == 1) (void)hipEventRecord(e0, c->stream);
@@ -730,11 +757,15 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, e0, e1);
     if (st != LBM_OK) break;
+    if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
+      std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d vec %d: %.4f ms/step\n", key.c_str(), cd[0],
+                   cd[1], cd[2], cd[3], ms / reps);
     if (ms < best) {
       best = ms;
       bb[0] = cd[0];
       bb[1] = cd[1];
       bb[2] = cd[2];
+      bb[3] = cd[3];
     }
   }
   (void)hipEventDestroy(e0);
@@ -751,8 +782,10 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   c->bx = bx0;
   c->by = by0;
   c->swz = swz0;
+  c->vec = vec0;
   lbm_status s2 = lbm_set_launch(c, bb[0], bb[1], bb[2]);
-  if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], best / reps);
+  if (s2 == LBM_OK) s2 = lbm_set_vectorized(c, bb[3]);
+  if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], bb[3], best / reps);
   return s2;
 }
 
@@ -761,12 +794,13 @@ extern "C" lbm_status lbm_copy_bandwidth(void *dst, const void *src, size_t byte
   if (bytes % 16 != 0) return fail(LBM_EINVAL, "bytes must be a multiple of 16");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t n = bytes / 16;
-  const unsigned blocks = unsigned(std::min<size_t>(65536, (n + 255) / 256));
+  if ((n + 255) / 256 > 0x7fffffffu) return fail(LBM_EINVAL, "copy too large for one launch");
+  const unsigned blocks = unsigned((n + 255) / 256);
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0), "event");
   HIPCHECK(hipEventCreate(&e1), "event");
-  uint4 *d = static_cast<uint4 *>(dst);
-  const uint4 *sp = static_cast<const uint4 *>(src);
+  lbm_v4u *d = static_cast<lbm_v4u *>(dst);
+  const lbm_v4u *sp = static_cast<const lbm_v4u *>(src);
   void *args[] = {&d, &sp, const_cast<size_t *>(&n)};
   HIPCHECK(hipLaunchKernel(copy_fn(), dim3(blocks), dim3(256), args, 0, s), "copy launch");
   HIPCHECK(hipEventRecord(e0, s), "event record");

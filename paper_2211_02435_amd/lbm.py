@@ -59,6 +59,8 @@ SIGNATURES = {
     "lbm_set_time": (c_int, [c_void_p, c_int64]),
     "lbm_set_launch": (c_int, [c_void_p, c_int, c_int, c_int]),
     "lbm_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+    "lbm_set_vectorized": (c_int, [c_void_p, c_int]),
+    "lbm_get_vectorized": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p]),
     "lbm_set_graphs": (c_int, [c_void_p, c_int]),
     "lbm_buffer": (c_int, [c_void_p, c_int, POINTER(c_void_p), POINTER(c_size_t)]),
@@ -245,6 +247,12 @@ class Lattice:
         a, b, c = c_int(), c_int(), c_int()
         check(self.lib.lbm_get_launch(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
         return a.value, b.value, c.value
+
+    def lbm_set_vectorized(self, enable):
+        check(self.lib.lbm_set_vectorized(self.ctx, 1 if enable else 0))
+
+    def lbm_get_vectorized(self):
+        return bool(self.lib.lbm_get_vectorized(self.ctx))
 
     def lbm_autotune(self):
         check(self.lib.lbm_autotune(self.ctx))

@@ -1,0 +1,130 @@
+"""Summaries of rocprofv3 output (rocpd SQLite databases) for the library's kernels.
+
+  python -m paper_2211_02435_amd.rocprof_summary stats <run_results.db> [--match sweep_kernel]
+      per-kernel calls, total and average duration (the --kernel-trace --stats view)
+
+  python -m paper_2211_02435_amd.rocprof_summary traffic --fetch <db> --write <db>
+      --kernel <substring> --copy-bytes <bytes> --workload <name> [--out <json>]
+      HBM bytes per launch of the kernel from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
+      each scaled by what the same counter reads for the plain copy kernel of known size,
+      together with the hash of the kernel sources the counters were taken on.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sqlite3
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+KERNEL_SOURCES = ["paper_2211_02435_amd/csrc/lbm_device.hpp", "paper_2211_02435_amd/csrc/lbm_kernels.hpp"]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_rows(db):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, duration, dispatch_id from kernels order by start").fetchall()
+    con.close()
+    return rows
+
+
+def stats(db, match=None):
+    agg = {}
+    for name, dur, _ in kernel_rows(db):
+        if match and match not in name:
+            continue
+        a = agg.setdefault(name, [0, 0.0, float("inf"), 0.0])
+        a[0] += 1
+        a[1] += dur
+        a[2] = min(a[2], dur)
+        a[3] = max(a[3], dur)
+    out = []
+    for name, (n, tot, mn, mx) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append({"kernel": name, "calls": n, "total_us": tot / 1e3, "avg_us": tot / n / 1e3,
+                    "min_us": mn / 1e3, "max_us": mx / 1e3})
+    return out
+
+
+def counter_per_dispatch(db, counter):
+    """{kernel name: [value per dispatch]} for one PMC counter (summed over instances)."""
+    con = sqlite3.connect(db)
+    q = """select k.name, k.dispatch_id, sum(p.value) from pmc_events p
+           join kernels k on p.event_id = k.id
+           join pmc_info i on p.pmc_id = i.id
+           where i.name = ? group by k.id order by k.start"""
+    try:
+        rows = con.execute(q, (counter,)).fetchall()
+    except sqlite3.OperationalError:
+        rows = []
+    if not rows:  # fall back to the counters_collection view
+        cols = [r[1] for r in con.execute("pragma table_info(counters_collection)")]
+        name_col = "kernel_name" if "kernel_name" in cols else "name"
+        rows = con.execute("select %s, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+                           "group by dispatch_id order by dispatch_id" % name_col, (counter,)).fetchall()
+    con.close()
+    out = {}
+    for name, _, v in rows:
+        out.setdefault(name, []).append(float(v))
+    return out
+
+
+def traffic(fetch_db, write_db, kernel, copy_bytes, workload):
+    f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
+    w = counter_per_dispatch(write_db, "WRITE_SIZE")
+
+    def pick(d, sub):
+        vals = [v for k, vs in d.items() if sub in k for v in vs]
+        if not vals:
+            raise SystemExit("no dispatch of a kernel matching %r" % sub)
+        vals.sort()
+        return vals[len(vals) // 2]  # median over dispatches
+
+    f_copy, w_copy = pick(f, "copy_kernel"), pick(w, "copy_kernel")
+    f_k, w_k = pick(f, kernel), pick(w, kernel)
+    sf, sw = copy_bytes / (f_copy * 1024.0), copy_bytes / (w_copy * 1024.0)
+    return {"workload": workload, "kernel_match": kernel, "kernel_source_sha": kernel_source_hash(),
+            "fetch_kib_per_launch_raw": f_k, "write_kib_per_launch_raw": w_k,
+            "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy, "copy_bytes_each_way": copy_bytes,
+            "fetch_scale": sf, "write_scale": sw,
+            "bytes_per_launch": f_k * 1024.0 * sf + w_k * 1024.0 * sw,
+            "fetch_bytes_per_launch": f_k * 1024.0 * sf, "write_bytes_per_launch": w_k * 1024.0 * sw}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--match", default=None)
+    t = sub.add_parser("traffic")
+    t.add_argument("--fetch", required=True)
+    t.add_argument("--write", required=True)
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--workload", required=True)
+    t.add_argument("--out", default=None)
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        rows = stats(a.db, a.match)
+        print("%-110s %6s %12s %10s %10s %10s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us"))
+        for r in rows:
+            print("%-110s %6d %12.1f %10.1f %10.1f %10.1f" % (r["kernel"][:110], r["calls"], r["total_us"],
+                                                               r["avg_us"], r["min_us"], r["max_us"]))
+    else:
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload)
+        txt = json.dumps(res, indent=1)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(txt + "\n")
+        print(txt)
+
+
+if __name__ == "__main__":
+    sys.exit(main())
