@@ -2,18 +2,20 @@
 
 Default workload: D3Q27 regularized cumulant method, 512^3 periodic box, Taylor-Green vortex
 (u0 = 0.05, Re = 1600 -> omega_s = 1.969902, all other rates 1), pull pattern, FP32 storage
-and compute (value) with the FP64 form on the same GPU beside it.  One step = one fused
-stream + collide sweep over all 134 M cells.  Inputs are resident in HBM before timing.
+and compute (value).  Reported beside it, on the same GPU: the plain FP64 single-box form,
+the batched ensemble form (256 D3Q27 central-moment boxes of edge 32..96, one launch per
+step, a 100-step hipGraph, FP32), the copy-kernel ceiling and the FP64 CPU oracle timed on a
+bounded sample.  One step = one fused stream + collide sweep over all cells.  Inputs are
+resident in HBM before timing; the hipGraph of the timed steps is recorded before timing.
 
-Prints one JSON line: MLUPS, roofline of the sweep kernel (algorithmic bytes 2 Q sizeof per
-lattice update over its HIP-event-timed average launch), the measured copy-kernel ceiling,
-the FP32-vs-FP64 velocity difference and the FP64 CPU oracle timed on a bounded sample.
+Prints one JSON line.  `roofline.achieved` = algorithmic bytes per launch (2 Q sizeof per
+lattice update) / average launch duration from HIP events on the library's stream.
 
-  python bench.py [--gpus 1] [--steps 200] [--warmup 10] [--workload d3q27_cumulant_512]
+  python bench.py [--gpus 1] [--steps 200] [--warmup 10]
+  python bench.py --workload d3q19_raw_256 | swe_d2q9_4096 | d2q9_central_64 | batch_d3q27_central
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,63 +29,101 @@ import lbm_workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
+SBYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def measured_traffic(workload, lups_per_launch):
+def measured_traffic(workload):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel source; else None."""
+    current kernel sources; else None."""
     path = TRAFFIC_FILE.format(workload=workload)
     if not os.path.exists(path):
         return None
+    from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
     with open(path) as f:
         t = json.load(f)
-    from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
     if t.get("kernel_source_sha") != kernel_source_hash():
         return None
     return t.get("bytes_per_launch")
 
 
-def build_workload(name):
-    cfg = W.WORKLOADS[name]
-    return cfg
+def workload_fields(name, cfg, n):
+    if name == "swe_d2q9_4096":
+        return W.swe_bumps(n, seed=0), (n, n, 1)
+    if name == "d2q9_central_64":
+        return W.tgv2d_fields(n, n, 1, u0=cfg["u0"]), (n, n, 1)
+    return W.tgv3d_fields(n, u0=cfg["u0"]), (n, n, n)
 
 
-def run_box(lbm, stencil, space, om, dims, storage, rho, u, steps, warmup, autotune, streaming="pull",
-            layout="auto"):
+def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout):
+    """Run one box: init, autotune, warm-up, record the graph, time `steps` sweeps."""
+    import oracle as O
     import torch
-    lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming, layout=layout)
-    lat.lbm_init_equilibrium(rho, u)
+    stencil, space = cfg["stencil"], cfg["space"]
+    om = O.regularized_rates(stencil, cfg["omega_shear"])
+    q = O.stencil(stencil).q
+    kw = {}
+    if cfg.get("equilibrium") == "swe":
+        kw = {"equilibrium": "swe", "gravity": cfg["gravity"]}
+    lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming, layout=layout, **kw)
+    lat.lbm_init_equilibrium(*fields)
     if autotune:
         lat.lbm_autotune()
     lat.lbm_step(warmup)
-    lat.lbm_graph_prepare(steps)  # record the hipGraph outside the timed region
+    lat.lbm_graph_prepare(steps)
     lat.lbm_synchronize()
-    # the timed region: graph replay of `steps` sweeps, bracketed by full synchronisation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ms_events = lat.lbm_time_steps(steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    return lat, wall, ms_events
+    cells = dims[0] * dims[1] * dims[2]
+    t_launch = ms_events / 1e3 / steps
+    gbs = 2 * q * SBYTES[storage] * cells / t_launch / 1e9
+    res = {"mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
+           "avg_launch_ms": t_launch * 1e3, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+           "bytes_per_lup": 2 * q * SBYTES[storage],
+           "launch_bx_by_swizzle_vec_lds": list(lat.lbm_get_launch()) + [int(lat.lbm_get_vectorized()),
+                                                                        lat.lbm_get_lds_reserve()]}
+    return lat, res
 
 
-def velocity_device(lat, lbm):
+def measure_batch(lbm, steps, warmup):
+    """The ensemble of 256 D3Q27 central-moment boxes (FP32), one launch per step, graph."""
+    import oracle as O
     import torch
-    nx, ny, nz = lat.dims
-    rho = torch.empty(nx * ny * nz, dtype=torch.float64, device="cuda")
-    u = torch.empty(3 * nx * ny * nz, dtype=torch.float64, device="cuda")
+    boxes = W.batch_ensemble(256, seed=0)
+    dims = [(b["edge"],) * 3 for b in boxes]
+    rates = [O.regularized_rates("D3Q27", b["omega_shear"]) for b in boxes]
+    fields = [W.batch_fields(b) for b in boxes]
+    rho = np.concatenate([f[0].ravel() for f in fields])
+    u = np.concatenate([f[1].ravel() for f in fields])
+    del fields
+    bat = lbm.Batch("D3Q27", "central", dims, rates, storage="f32")
+    bat.lbm_batch_init_equilibrium(rho, u)
+    del rho, u
+    bat.lbm_batch_step(warmup)
+    bat.lbm_batch_graph_prepare(steps)
+    bat.lbm_batch_synchronize()
     torch.cuda.synchronize()
-    lbm.check(lat.lib.lbm_macroscopic(lat.ctx, lbm._dptr(rho), lbm._dptr(u)))
-    return rho, u
+    t0 = time.perf_counter()
+    ms = bat.lbm_batch_time_steps(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = bat.lbm_batch_cells()
+    gbs = 216 * cells / (ms / 1e3 / steps) / 1e9
+    return {"boxes": len(boxes), "cells": cells, "steps": steps, "graph_steps": steps,
+            "mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
+            "avg_launch_ms": ms / steps, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "storage": "f32", "space": "central"}
 
 
-def cpu_baseline(stencil, space, om, n, steps):
+def cpu_baseline(cfg, n, steps):
     """The FP64 oracle, single-threaded, on an n^3 copy of the Taylor-Green workload."""
     from threadpoolctl import threadpool_limits
     import oracle as O
     with threadpool_limits(limits=1):
-        m = O.Method(stencil, space, om)
-        rho, u = W.tgv3d_fields(n, u0=0.05)
+        m = O.Method(cfg["stencil"], cfg["space"], O.regularized_rates(cfg["stencil"], cfg["omega_shear"]))
+        rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
         df = O.init_equilibrium(m, rho, u)
         t0 = time.perf_counter()
         O.step(m, df, steps)
@@ -93,14 +133,40 @@ def cpu_baseline(stencil, space, om, n, steps):
                       "Taylor-Green workload, %d steps, %.1f s" % (n, steps, dt)}
 
 
+def copy_ceiling(lbm):
+    import torch
+    nbytes = 4 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    ms = lbm.lbm_copy_bandwidth(b, a, nbytes, 20)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes * 20 / (ms / 1e3) / 1e9
+
+
+def velocity_rel_diff(lbm, lat_a, lat_b):
+    import torch
+    n = lat_a.ncells
+    us = []
+    for lat in (lat_a, lat_b):
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        v = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        lbm.check(lat.lib.lbm_macroscopic(lat.ctx, lbm._dptr(r), lbm._dptr(v)))
+        us.append(v)
+        del r
+    return float(torch.linalg.norm(us[0] - us[1]) / torch.linalg.norm(us[1]))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="d3q27_cumulant_512")
+    ap.add_argument("--workload", default="d3q27_cumulant_512", choices=sorted(W.WORKLOADS))
     ap.add_argument("--size", type=int, default=0, help="override the edge length (smaller boxes)")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "planes", "rows"])
@@ -110,95 +176,96 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the sweep would shard "
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (a box would shard "
               "as z-slabs with one halo exchange per step; not built).", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_2211_02435_amd import lbm
-    import oracle as O  # rates helper for the workload definition and the cpu baseline
 
-    cfg = build_workload(args.workload)
-    stencil, space = cfg["stencil"], cfg["space"]
+    name = args.workload
+    cfg = W.WORKLOADS[name]
+    if name == "batch_d3q27_central":
+        res = measure_batch(lbm, args.steps, args.warmup)
+        out = {"metric": "MLUPS and % of HBM roofline, batched ensemble of 256 D3Q27 central-moment boxes",
+               "value": res["mlups"], "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+               "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic Taylor-Green boxes",
+               "config": {"workload": "256 periodic D3Q27 central-moment boxes, edges 32..96, seed 0"},
+               "roofline": {"bound": "hbm", "achieved": res["achieved_GBps"], "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": res["frac"], "traffic": None}, "batch": res}
+        print(json.dumps(out), flush=True)
+        return
+
     n = args.size or cfg["dims"][0]
-    dims = (n, n, n)
-    om = O.regularized_rates(stencil, cfg["omega_shear"])
-    q = O.stencil(stencil).q
-    rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
-    cells = n ** 3
-    print("[bench] %s %s %d^3, steps %d, warmup %d" % (stencil, space, n, args.steps, args.warmup),
+    fields, dims = workload_fields(name, cfg, n)
+    storages = {"swe_d2q9_4096": ["f16", "f64"], "d2q9_central_64": ["f64"]}.get(name, ["f32", "f64"])
+    if args.no_fp64:
+        storages = [s for s in storages if s != "f64"] or storages[:1]
+    print("[bench] %s %s dims %s, steps %d, warmup %d" % (name, storages, dims, args.steps, args.warmup),
           file=sys.stderr, flush=True)
-
-    # FP32 (value)
-    lat32, wall32, ev32 = run_box(lbm, stencil, space, om, dims, "f32", rho, u, args.steps, args.warmup,
-                                  not args.no_autotune, args.streaming, args.layout)
-    mlups32 = cells * args.steps / wall32 / 1e6
-    bytes32 = 2 * q * 4 * cells
-    t_launch32 = ev32 / 1e3 / args.steps
-    achieved32 = bytes32 / t_launch32 / 1e9
-    launch32 = list(lat32.lbm_get_launch()) + [int(lat32.lbm_get_vectorized())]
-    print("[bench] fp32 done: %.0f MLUPS, %.1f GB/s" % (mlups32, achieved32), file=sys.stderr, flush=True)
-
-    result_fp64 = None
-    vel_err = None
-    if not args.no_fp64:
-        lat64, wall64, ev64 = run_box(lbm, stencil, space, om, dims, "f64", rho, u, args.steps, args.warmup,
-                                      not args.no_autotune, args.streaming, args.layout)
-        t_launch64 = ev64 / 1e3 / args.steps
-        result_fp64 = {"mlups": cells * args.steps / wall64 / 1e6,
-                       "ms_per_step": wall64 * 1e3 / args.steps,
-                       "achieved_GBps": 2 * q * 8 * cells / t_launch64 / 1e9,
-                       "frac": 2 * q * 8 * cells / t_launch64 / 1e9 / HBM_PEAK_GBS,
-                       "launch": list(lat64.lbm_get_launch()) + [int(lat64.lbm_get_vectorized())]}
-        _, u32 = velocity_device(lat32, lbm)
-        _, u64 = velocity_device(lat64, lbm)
-        vel_err = float(torch.linalg.norm(u32 - u64) / torch.linalg.norm(u64))
-        del u32, u64
-        lat64.close()
-        print("[bench] fp64 done: %.0f MLUPS" % result_fp64["mlups"], file=sys.stderr, flush=True)
-    lat32.close()
+    runs, lats = {}, {}
+    for st in storages:
+        lat, res = measure_box(lbm, cfg, st, fields, dims, args.steps, args.warmup,
+                               not args.no_autotune, args.streaming, args.layout)
+        runs[st], lats[st] = res, lat
+        print("[bench] %s: %.0f MLUPS, %.1f GB/s" % (st, res["mlups"], res["achieved_GBps"]),
+              file=sys.stderr, flush=True)
+    del fields
+    main_st = storages[0]
+    vel = None
+    if "f64" in lats and main_st != "f64":
+        vel = velocity_rel_diff(lbm, lats[main_st], lats["f64"])
+    for lat in lats.values():
+        lat.close()
+    lats.clear()
     torch.cuda.empty_cache()
 
-    # copy-kernel ceiling on 4 GiB
-    nbytes = 4 << 30
-    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    b = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
-    ms = lbm.lbm_copy_bandwidth(b, a, nbytes, 20)
-    copy_gbs = 2 * nbytes * 20 / (ms / 1e3) / 1e9
-    del a, b
-
+    is_metric = name == "d3q27_cumulant_512" and n == cfg["dims"][0]
+    batch = None
+    if is_metric and not args.no_batch:
+        batch = measure_batch(lbm, 100, args.warmup)
+        print("[bench] batch: %.0f MLUPS" % batch["mlups"], file=sys.stderr, flush=True)
+    ceiling = copy_ceiling(lbm)
     cpu = None
-    if not args.no_cpu:
-        cpu = cpu_baseline(stencil, space, om, args.cpu_size, args.cpu_steps)
+    if is_metric and not args.no_cpu:
+        cpu = cpu_baseline(cfg, args.cpu_size, args.cpu_steps)
 
-    workload = "%s %s %d^3 periodic Taylor-Green (u0 %.2f, omega_s %.6f, other rates 1), %s" % (
-        stencil, space, n, cfg["u0"], cfg["omega_shear"], args.streaming)
+    r = runs[main_st]
+    fields_desc = ("shallow water g 0.1, 16 Gaussian bumps" if name == "swe_d2q9_4096"
+                   else "Taylor-Green u0 %.2f" % cfg["u0"])
+    workload = "%s %s %s periodic, %s, omega_s %.6f, other rates 1, %s" % (
+        cfg["stencil"], cfg["space"], "x".join(str(d) for d in dims), fields_desc, cfg["omega_shear"],
+        args.streaming)
     out = {
-        "metric": "MLUPS and % of HBM roofline, D3Q27 cumulant 512^3, FP32 vs FP64",
-        "value": mlups32,
+        "metric": ("MLUPS and % of HBM roofline, D3Q27 cumulant 512^3, FP32 vs FP64" if is_metric
+                   else "MLUPS and % of HBM roofline, " + name),
+        "value": r["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall32 * 1e3 / args.steps,
+        "ms_per_step": r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic Taylor-Green vortex initial fields",
-        "config": {"workload": workload, "cells": cells, "stencil": stencil, "space": space,
-                   "storage": "f32", "streaming": args.streaming,
-                   "layout": args.layout if args.layout != "auto" else "planes (auto for f32)",
-                   "launch_bx_by_swizzle_vec": launch32},
-        "roofline": {"bound": "hbm", "achieved": achieved32, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved32 / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(args.workload if n == cfg["dims"][0] else "none", cells),
-                     "kernel": "sweep_kernel<D3Q27, CUMULANT, regularized, f32, pull>",
-                     "bytes_per_lup": 2 * q * 4,
-                     "avg_launch_ms": t_launch32 * 1e3},
-        "fp64": result_fp64,
-        "fp32_vs_fp64_velocity_rel_l2": vel_err,
-        "copy_ceiling_GBps": copy_gbs,
+        "dtype": main_st,
+        "data": "synthetic initial fields (Taylor-Green vortex / Gaussian water bumps)",
+        "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
+                   "layout": args.layout, "streaming": args.streaming,
+                   "launch_bx_by_swizzle_vec_lds": r["launch_bx_by_swizzle_vec_lds"]},
+        "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": r["frac"],
+                     "traffic": measured_traffic(name) if (n == cfg["dims"][0] and main_st == "f32"
+                                                           and args.layout == "auto"
+                                                           and args.streaming == "pull") else None,
+                     "kernel": "sweep_kernel<%s, %s, regularized, %s, %s>" % (cfg["stencil"], cfg["space"],
+                                                                              main_st, args.streaming),
+                     "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},
+        "fp64": runs.get("f64") if main_st != "f64" else None,
+        "velocity_rel_l2_vs_fp64": vel,
+        "batched": batch,
+        "copy_ceiling_GBps": ceiling,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -191,7 +191,14 @@ lbm_status lbm_get_launch(const lbm_ctx *ctx, int *bx, int *by, int *xcd_swizzle
 lbm_status lbm_set_vectorized(lbm_ctx *ctx, int enable);
 int lbm_get_vectorized(const lbm_ctx *ctx);
 
-/* Time candidate launch shapes (block shape, XCD swizzle, vectorised or per-cell kernel) on
+/* Dynamic LDS reserved by every sweep block (0 .. 65536 bytes; the sweep itself uses none):
+ * caps the resident blocks per CU (160 KB of LDS each), i.e. the number of waves streaming
+ * concurrently.  0 by default; lbm_autotune considers it. */
+lbm_status lbm_set_lds_reserve(lbm_ctx *ctx, int bytes);
+int lbm_get_lds_reserve(const lbm_ctx *ctx);
+
+/* Time candidate launch shapes (block shape, XCD swizzle, vectorised or per-cell kernel, then
+ * the LDS reserve of the best shape) on
  * the context's own buffers (state is left unchanged) and keep the fastest; results are
  * cached per (method, precision, pattern, layout, size) in the JSON file named by
  * LBM_AUTOTUNE_CACHE, if set. */
@@ -232,6 +239,8 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_graph_prepare(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u);
 lbm_status lbm_batch_get_populations(lbm_batch *b, double *df);
+/* df(t) of box k alone, natural layout df[i * ncells_k + cell] (q * ncells_k doubles). */
+lbm_status lbm_batch_get_box_populations(lbm_batch *b, int k, double *df);
 lbm_status lbm_batch_synchronize(lbm_batch *b);
 int64_t lbm_batch_cells(const lbm_batch *b);
 lbm_status lbm_batch_set_graphs(lbm_batch *b, int enable);

@@ -58,6 +58,34 @@ def tgv3d_fields(nx, ny=None, nz=None, u0=0.05, phase=(0.0, 0.0, 0.0), period=No
     return np.ascontiguousarray(rho), np.ascontiguousarray(u)
 
 
+def tgv3d_points(ix, iy, iz, n, u0=0.05, phase=(0.0, 0.0, 0.0)):
+    """The fields of tgv3d_fields(n, u0=u0, phase=phase) at integer nodes (ix, iy, iz) only
+    (same formula, evaluated point by point): rho (m,), u (m, 3)."""
+    k = 2.0 * math.pi / n
+    ax = k * np.asarray(ix, dtype=np.float64) + phase[0]
+    ay = k * np.asarray(iy, dtype=np.float64) + phase[1]
+    az = k * np.asarray(iz, dtype=np.float64) + phase[2]
+    ux = u0 * np.sin(ax) * np.cos(ay) * np.cos(az)
+    uy = -u0 * np.cos(ax) * np.sin(ay) * np.cos(az)
+    rho = 1.0 + 3.0 * (u0 * u0 / 16.0) * (np.cos(2 * ax) + np.cos(2 * ay)) * (np.cos(2 * az) + 2.0)
+    return rho, np.stack([ux, uy, np.zeros_like(ux)], axis=1)
+
+
+def sample_cells(dims, count, seed=0):
+    """Distinct sample cells (x, y, z): the eight box corners, cells on each face, the rest
+    uniform; returns an int array (m, 3)."""
+    nx, ny, nz = dims
+    rng = np.random.default_rng(seed)
+    pts = {(x, y, z) for x in (0, nx - 1) for y in (0, ny - 1) for z in (0, nz - 1)}
+    for _ in range(count):
+        p = [int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz))]
+        face = int(rng.integers(0, 4))
+        if face < 3:
+            p[face] = 0 if rng.random() < 0.5 else (nx, ny, nz)[face] - 1
+        pts.add(tuple(p))
+    return np.array(sorted(pts), dtype=np.int64)
+
+
 def swe_bumps(n, seed=0, nbumps=16, amp=0.1, sigma=(20.0, 100.0)):
     """Water height h = 1 + amp * sum_b exp(-d_per(x, c_b)^2 / (2 sigma_b^2)) on an n x n
     periodic grid, centres c_b uniform in [0, n)^2, sigma_b uniform in [20, 100] cells,

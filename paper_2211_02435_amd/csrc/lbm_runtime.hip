@@ -117,6 +117,7 @@ struct lbm_ctx {
   bool own_stream = false;
   int bx = 64, by = 4, swz = 0;
   bool vec = false;   // vectorised sweep (V cells per lane) where the shape allows it
+  int lds = 0;        // dynamic LDS reserved per sweep block: caps resident blocks per CU
   bool graphs = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
@@ -163,7 +164,7 @@ static hipError_t launch_sweep_t(const lbm_ctx *c, const void *fn, const void *s
   SweepArgs<ST, CT> a = make_sweep_args<ST, CT>(c, src, dst, vec);
   void *args[] = {&a};
   const dim3 grid(unsigned(uint64_t(a.tiles_x) * uint64_t(a.tiles_y) * uint64_t(c->nz)));
-  return hipLaunchKernel(fn, grid, dim3(c->bx, c->by), args, 0, c->stream);
+  return hipLaunchKernel(fn, grid, dim3(c->bx, c->by), args, size_t(c->lds), c->stream);
 }
 
 static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src, void *dst, bool vec) {
@@ -606,6 +607,16 @@ extern "C" lbm_status lbm_set_vectorized(lbm_ctx *c, int enable) {
 
 extern "C" int lbm_get_vectorized(const lbm_ctx *c) { return c && c->vec ? 1 : 0; }
 
+extern "C" lbm_status lbm_set_lds_reserve(lbm_ctx *c, int bytes) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (bytes < 0 || bytes > 65536) return fail(LBM_EINVAL, "LDS reserve must be in [0, 65536] bytes");
+  if (c->lds != bytes) clear_graphs(c);
+  c->lds = bytes;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_lds_reserve(const lbm_ctx *c) { return c ? c->lds : -1; }
+
 extern "C" lbm_status lbm_get_launch(const lbm_ctx *c, int *bx, int *by, int *swz) {
   if (!c || !bx || !by || !swz) return fail(LBM_EINVAL, "NULL argument");
   *bx = c->bx;
@@ -656,7 +667,8 @@ static std::string tune_key(const lbm_ctx *c) {
   return k.str();
 }
 
-static bool cache_lookup(const std::string &file, const std::string &key, int *bx, int *by, int *swz, int *vec) {
+static bool cache_lookup(const std::string &file, const std::string &key, int *bx, int *by, int *swz, int *vec,
+                         int *lds) {
   std::ifstream in(file);
   if (!in) return false;
   std::string line;
@@ -667,12 +679,12 @@ static bool cache_lookup(const std::string &file, const std::string &key, int *b
     size_t lb = line.find('[', p);
     if (lb == std::string::npos) continue;
     double ms = 0;
-    if (std::sscanf(line.c_str() + lb, "[%d, %d, %d, %d, %lf", bx, by, swz, vec, &ms) >= 4) return true;
+    if (std::sscanf(line.c_str() + lb, "[%d, %d, %d, %d, %d, %lf", bx, by, swz, vec, lds, &ms) >= 5) return true;
   }
   return false;
 }
 
-static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, int vec,
+static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, int vec, int lds,
                         double ms) {
   std::vector<std::string> lines;
   {
@@ -686,7 +698,7 @@ static void cache_store(const std::string &file, const std::string &key, int bx,
     }
   }
   char buf[256];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %.6f]", key.c_str(), bx, by, swz, vec, ms);
+  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %.6f]", key.c_str(), bx, by, swz, vec, lds, ms);
   lines.push_back(buf);
   std::ofstream out(file, std::ios::trunc);
   out << "{\n";
@@ -698,10 +710,11 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   const char *file = std::getenv("LBM_AUTOTUNE_CACHE");
   const std::string key = tune_key(c);
-  int bx, by, swz, vec = 0;
-  if (file && cache_lookup(file, key, &bx, &by, &swz, &vec)) {
+  int bx, by, swz, vec = 0, lds = 0;
+  if (file && cache_lookup(file, key, &bx, &by, &swz, &vec, &lds)) {
     lbm_status s0 = lbm_set_launch(c, bx, by, swz);
-    return s0 != LBM_OK ? s0 : lbm_set_vectorized(c, vec);
+    if (s0 == LBM_OK) s0 = lbm_set_vectorized(c, vec);
+    return s0 != LBM_OK ? s0 : lbm_set_lds_reserve(c, lds);
   }
   // candidate shapes: (bx, by, swizzle, vectorised)
   std::vector<std::array<int, 4>> cand;
@@ -728,8 +741,9 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   }
   const int cur0 = c->cur;
   const int64_t t0 = c->t;
-  const int bx0 = c->bx, by0 = c->by, swz0 = c->swz;
+  const int bx0 = c->bx, by0 = c->by, swz0 = c->swz, lds0 = c->lds;
   const bool vec0 = c->vec;
+  c->lds = 0;
   const bool g0 = c->graphs;
   c->graphs = false;
   const uint64_t lups = uint64_t(c->ncells);
@@ -768,6 +782,36 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
       bb[3] = cd[3];
     }
   }
+  // phase 2: occupancy cap for the best shape (dynamic LDS per block)
+  int best_lds = 0;
+  if (st == LBM_OK) {
+    c->bx = bb[0];
+    c->by = bb[1];
+    c->swz = bb[2];
+    c->vec = bb[3] != 0;
+    for (int lds : {16384, 24576, 32768, 40960, 54272}) {
+      c->lds = lds;
+      for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
+        if (r == 1) (void)hipEventRecord(e0, c->stream);
+        c->cur = cur0;
+        c->t = t0;
+        st = one_step(c);
+      }
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (st != LBM_OK) break;
+      if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
+        std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d vec %d lds %d: %.4f ms/step\n", key.c_str(),
+                     bb[0], bb[1], bb[2], bb[3], lds, ms / reps);
+      if (ms < best) {
+        best = ms;
+        best_lds = lds;
+      }
+    }
+    c->lds = lds0;
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->cur = cur0;
@@ -785,7 +829,8 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   c->vec = vec0;
   lbm_status s2 = lbm_set_launch(c, bb[0], bb[1], bb[2]);
   if (s2 == LBM_OK) s2 = lbm_set_vectorized(c, bb[3]);
-  if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], bb[3], best / reps);
+  if (s2 == LBM_OK) s2 = lbm_set_lds_reserve(c, best_lds);
+  if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], bb[3], best_lds, best / reps);
   return s2;
 }
 
@@ -1160,6 +1205,24 @@ extern "C" lbm_status lbm_batch_get_populations(lbm_batch *b, double *df) {
              "copy populations");
     HIPCHECK(hipStreamSynchronize(b->stream), "populations sync");
   }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_get_box_populations(lbm_batch *b, int k, double *df) {
+  if (!b || !df) return fail(LBM_EINVAL, "NULL argument");
+  if (k < 0 || k >= b->nboxes) return fail(LBM_EINVAL, "box index out of range");
+  const BoxInfo &B = b->boxes[k];
+  lbm_status s = batch_staging(b, size_t(b->q) * B.ncells);
+  if (s != LBM_OK) return s;
+  FieldArgs a = batch_field(b, k, b->buf[b->cur]);
+  a.pop = b->staging;
+  a.i0 = 0;
+  a.i1 = b->q;
+  s = batch_launch_field(b, export_fn(b->s, b->store, G_SHIFTED), a);
+  if (s != LBM_OK) return s;
+  HIPCHECK(hipMemcpyAsync(df, b->staging, size_t(b->q) * B.ncells * sizeof(double), hipMemcpyDefault, b->stream),
+           "copy populations");
+  HIPCHECK(hipStreamSynchronize(b->stream), "populations sync");
   return LBM_OK;
 }
 

@@ -61,6 +61,8 @@ SIGNATURES = {
     "lbm_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     "lbm_set_vectorized": (c_int, [c_void_p, c_int]),
     "lbm_get_vectorized": (c_int, [c_void_p]),
+    "lbm_set_lds_reserve": (c_int, [c_void_p, c_int]),
+    "lbm_get_lds_reserve": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p]),
     "lbm_set_graphs": (c_int, [c_void_p, c_int]),
     "lbm_buffer": (c_int, [c_void_p, c_int, POINTER(c_void_p), POINTER(c_size_t)]),
@@ -74,6 +76,7 @@ SIGNATURES = {
     "lbm_batch_graph_prepare": (c_int, [c_void_p, c_int64]),
     "lbm_batch_macroscopic": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_batch_get_populations": (c_int, [c_void_p, c_void_p]),
+    "lbm_batch_get_box_populations": (c_int, [c_void_p, c_int, c_void_p]),
     "lbm_batch_synchronize": (c_int, [c_void_p]),
     "lbm_batch_cells": (c_int64, [c_void_p]),
     "lbm_batch_set_graphs": (c_int, [c_void_p, c_int]),
@@ -254,6 +257,12 @@ class Lattice:
     def lbm_get_vectorized(self):
         return bool(self.lib.lbm_get_vectorized(self.ctx))
 
+    def lbm_set_lds_reserve(self, nbytes):
+        check(self.lib.lbm_set_lds_reserve(self.ctx, int(nbytes)))
+
+    def lbm_get_lds_reserve(self):
+        return int(self.lib.lbm_get_lds_reserve(self.ctx))
+
     def lbm_autotune(self):
         check(self.lib.lbm_autotune(self.ctx))
 
@@ -318,6 +327,12 @@ class Batch:
     def lbm_batch_get_populations(self):
         df = np.empty(self.q * sum(self.ncells))
         check(self.lib.lbm_batch_get_populations(self.b, _dptr(df)))
+        return df
+
+    def lbm_batch_get_box_populations(self, k):
+        nx, ny, nz = self.dims[k]
+        df = np.empty((self.q, nz, ny, nx))
+        check(self.lib.lbm_batch_get_box_populations(self.b, int(k), _dptr(df)))
         return df
 
     def lbm_batch_synchronize(self):
