@@ -54,7 +54,7 @@ def workload_fields(name, cfg, n):
     return W.tgv3d_fields(n, u0=cfg["u0"]), (n, n, n)
 
 
-def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout):
+def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout, transform="chimera"):
     """Run one box: init, autotune, warm-up, record the graph, time `steps` sweeps."""
     import oracle as O
     import torch
@@ -68,6 +68,12 @@ def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, stream
     lat.lbm_init_equilibrium(*fields)
     if autotune:
         lat.lbm_autotune()
+    if transform != "chimera":
+        bx, by, _ = lat.lbm_get_launch()
+        if bx * by > 256:  # the ablation kernel takes at most four waves per block
+            nbx = min(bx, 256)
+            lat.lbm_set_launch(nbx, max(1, 256 // nbx), 1)
+        lat.lbm_set_transform(transform)
     lat.lbm_step(warmup)
     lat.lbm_graph_prepare(steps)
     lat.lbm_synchronize()
@@ -83,7 +89,8 @@ def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, stream
            "avg_launch_ms": t_launch * 1e3, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
            "bytes_per_lup": 2 * q * SBYTES[storage],
            "launch_bx_by_swizzle_vec_lds": list(lat.lbm_get_launch()) + [int(lat.lbm_get_vectorized()),
-                                                                        lat.lbm_get_lds_reserve()]}
+                                                                        lat.lbm_get_lds_reserve()],
+           "transform": lat.lbm_get_transform()}
     return lat, res
 
 
@@ -171,6 +178,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "planes", "rows"])
     ap.add_argument("--streaming", default="pull", choices=["pull", "aa"])
+    ap.add_argument("--transform", default="chimera", choices=["chimera", "dense_mfma"],
+                    help="dense_mfma: the measured ablation of the raw-moment transform on MFMA")
     ap.add_argument("--cpu-size", type=int, default=32)
     ap.add_argument("--cpu-steps", type=int, default=40)
     args = ap.parse_args()
@@ -207,7 +216,7 @@ def main():
     runs, lats = {}, {}
     for st in storages:
         lat, res = measure_box(lbm, cfg, st, fields, dims, args.steps, args.warmup,
-                               not args.no_autotune, args.streaming, args.layout)
+                               not args.no_autotune, args.streaming, args.layout, args.transform)
         runs[st], lats[st] = res, lat
         print("[bench] %s: %.0f MLUPS, %.1f GB/s" % (st, res["mlups"], res["achieved_GBps"]),
               file=sys.stderr, flush=True)
@@ -252,13 +261,13 @@ def main():
         "dtype": main_st,
         "data": "synthetic initial fields (Taylor-Green vortex / Gaussian water bumps)",
         "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
-                   "layout": args.layout, "streaming": args.streaming,
+                   "layout": args.layout, "streaming": args.streaming, "transform": args.transform,
                    "launch_bx_by_swizzle_vec_lds": r["launch_bx_by_swizzle_vec_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
                      "traffic": measured_traffic(name) if (n == cfg["dims"][0] and main_st == "f32"
-                                                           and args.layout == "auto"
-                                                           and args.streaming == "pull") else None,
+                                                           and args.layout == "auto" and args.streaming == "pull"
+                                                           and args.transform == "chimera") else None,
                      "kernel": "sweep_kernel<%s, %s, regularized, %s, %s>" % (cfg["stencil"], cfg["space"],
                                                                               main_st, args.streaming),
                      "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},

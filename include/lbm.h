@@ -191,6 +191,15 @@ lbm_status lbm_get_launch(const lbm_ctx *ctx, int *bx, int *by, int *xcd_swizzle
 lbm_status lbm_set_vectorized(lbm_ctx *ctx, int enable);
 int lbm_get_vectorized(const lbm_ctx *ctx);
 
+/* Collision-space transform of the sweep.  CHIMERA (default): the raw-moment Chimera passes
+ * of sec. 4.1.1 in registers.  DENSE_MFMA (measured ablation): m = M df and df* = M^-1 dm* as
+ * dense 27 x 27 products over the 64 cells of a wave on the matrix cores, staged through
+ * LDS; D3Q27, pull, Maxwellian equilibrium, blocks of 64..256 threads (LBM_EUNSUPPORTED
+ * otherwise; a later lbm_set_launch with more threads reverts to CHIMERA). */
+typedef enum { LBM_TRANSFORM_CHIMERA = 0, LBM_TRANSFORM_DENSE_MFMA = 1 } lbm_transform;
+lbm_status lbm_set_transform(lbm_ctx *ctx, int transform);
+int lbm_get_transform(const lbm_ctx *ctx);
+
 /* Dynamic LDS reserved by every sweep block (0 .. 65536 bytes; the sweep itself uses none):
  * caps the resident blocks per CU (160 KB of LDS each), i.e. the number of waves streaming
  * concurrently.  0 by default; lbm_autotune considers it. */

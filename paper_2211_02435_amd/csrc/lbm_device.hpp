@@ -424,73 +424,77 @@ LBM_HD void swe_feq_dev(T *g9, T dh, T h, T ux, T uy, T grav) {
 }
 
 // ---------------------------------------------------------------------------------------
+// the collision in moment space: m holds dm = M df (exponent-grid order) on entry and the
+// post-collision dm* on exit.  Missing monomials (D3Q19) leave as zero.
+// ---------------------------------------------------------------------------------------
+template <int S, int SP, int EQ, bool REG, class T>
+LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav) {
+  constexpr int D = Lat<S>::D;
+  constexpr int G = Lat<S>::G;
+  constexpr int EX = 1, EY = 3, EZ = 9;
+  const T drho = m[0];
+  const T jx = m[EX], jy = m[EY];
+  const T jz = (D == 3) ? m[EZ] : T(0);
+  const T rho = T(1) + drho;
+  const T rinv = T(1) / rho;
+  T u[3] = {jx * rinv, jy * rinv, jz * rinv};
+  T uu[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
+
+  // equilibrium moments (deviation form)
+  T meq[G];
+  if constexpr (EQ == SWE) {
+    swe_feq_dev(meq, drho, rho, u[0], u[1], grav);
+    chimera_forward<S>(meq);
+  } else {
+    sfor<G>([&](auto E) {
+      constexpr int e = decltype(E)::value;
+      if constexpr (Lat<S>::has_mono_e(e)) meq[e] = meq_dev<e, SP == RAW>(drho, rho, u, uu);
+      else meq[e] = T(0);
+    });
+    meq[EX] = jx;
+    meq[EY] = jy;
+    if constexpr (D == 3) meq[EZ] = jz;
+  }
+
+  // non-equilibrium raw moments (orders >= 2)
+  T v[G];
+  sfor<G>([&](auto E) {
+    constexpr int e = decltype(E)::value;
+    if constexpr (Lat<S>::ord(e) < 2) v[e] = T(0);
+    else if constexpr (REG && Lat<S>::ord(e) > 2) v[e] = T(0);
+    else v[e] = m[e] - meq[e];
+  });
+
+  if constexpr (SP == RAW) {
+    relax<S, REG>(v, R);
+  } else {
+    // to central moments; with zero orders 0, 1 the order-2 entries are unchanged
+    if constexpr (!REG) binomial<S>(v, -u[0], -u[1], -u[2]);
+    if constexpr (SP == CENTRAL) {
+      relax<S, REG>(v, R);
+    } else {
+      if constexpr (!REG) cumulant_map<S, -1, false>(v, rinv);
+      relax<S, REG>(v, R);
+      cumulant_map<S, +1, REG>(v, rinv);
+    }
+    binomial<S>(v, u[0], u[1], u[2]);
+  }
+  // dm* = dm_eq + non-equilibrium part; conserved moments exactly
+  sfor<G>([&](auto E) {
+    constexpr int e = decltype(E)::value;
+    if constexpr (!Lat<S>::has_mono_e(e)) m[e] = T(0);
+    else if constexpr (Lat<S>::ord(e) >= 2) m[e] = meq[e] + v[e];
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // the collision: g holds df (grid order, missing velocities zero) and receives df*
 // ---------------------------------------------------------------------------------------
 template <int S, int SP, int EQ, bool REG, class T>
 LBM_HD void collide(T *g, const Relax<T> &R, T grav) {
-  if constexpr (SP == IDENTITY) {
-    return;
-  } else {
-    constexpr int D = Lat<S>::D;
-    constexpr int G = Lat<S>::G;
-    constexpr int EX = 1, EY = 3, EZ = 9;
-    T m[G];
-    sfor<G>([&](auto E) { m[E] = g[E]; });
-    chimera_forward<S>(m);
-    const T drho = m[0];
-    const T jx = m[EX], jy = m[EY];
-    const T jz = (D == 3) ? m[EZ] : T(0);
-    const T rho = T(1) + drho;
-    const T rinv = T(1) / rho;
-    T u[3] = {jx * rinv, jy * rinv, jz * rinv};
-    T uu[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
-
-    // equilibrium moments (deviation form)
-    T meq[G];
-    if constexpr (EQ == SWE) {
-      swe_feq_dev(meq, drho, rho, u[0], u[1], grav);
-      chimera_forward<S>(meq);
-    } else {
-      sfor<G>([&](auto E) {
-        constexpr int e = decltype(E)::value;
-        if constexpr (Lat<S>::has_mono_e(e)) meq[e] = meq_dev<e, SP == RAW>(drho, rho, u, uu);
-        else meq[e] = T(0);
-      });
-      meq[EX] = jx;
-      meq[EY] = jy;
-      if constexpr (D == 3) meq[EZ] = jz;
-    }
-
-    // non-equilibrium raw moments (orders >= 2)
-    T v[G];
-    sfor<G>([&](auto E) {
-      constexpr int e = decltype(E)::value;
-      if constexpr (Lat<S>::ord(e) < 2) v[e] = T(0);
-      else if constexpr (REG && Lat<S>::ord(e) > 2) v[e] = T(0);
-      else v[e] = m[e] - meq[e];
-    });
-
-    if constexpr (SP == RAW) {
-      relax<S, REG>(v, R);
-    } else {
-      // to central moments; with zero orders 0, 1 the order-2 entries are unchanged
-      if constexpr (!REG) binomial<S>(v, -u[0], -u[1], -u[2]);
-      if constexpr (SP == CENTRAL) {
-        relax<S, REG>(v, R);
-      } else {
-        if constexpr (!REG) cumulant_map<S, -1, false>(v, rinv);
-        relax<S, REG>(v, R);
-        cumulant_map<S, +1, REG>(v, rinv);
-      }
-      binomial<S>(v, u[0], u[1], u[2]);
-    }
-    // dm* = dm_eq + non-equilibrium part; conserved moments exactly
-    sfor<G>([&](auto E) {
-      constexpr int e = decltype(E)::value;
-      if constexpr (!Lat<S>::has_mono_e(e)) g[e] = T(0);
-      else if constexpr (Lat<S>::ord(e) < 2) g[e] = m[e];
-      else g[e] = meq[e] + v[e];
-    });
+  if constexpr (SP != IDENTITY) {
+    chimera_forward<S>(g);
+    collide_moments<S, SP, EQ, REG, T>(g, R, grav);
     chimera_inverse<S>(g);
   }
 }

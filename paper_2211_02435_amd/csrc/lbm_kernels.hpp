@@ -104,13 +104,18 @@ struct Nbr {
   __device__ __forceinline__ uint32_t lane(int cx, int cy, int s) const { return yoff[1 + s * cy] + xs[1 + s * cx]; }
 };
 
+// The lane part is turned into a 32-bit byte offset (lane * sizeof(ST) < 2^32 by validation of
+// the z-plane size), so the compiler can address with a scalar 64-bit base plus a 32-bit
+// vector offset instead of a 64-bit address per lane.
 template <class ST>
 __device__ __forceinline__ ST ldp(const ST *base, uint64_t uniform, uint32_t lane) {
-  return (base + uniform)[lane];
+  const uint32_t boff = lane * uint32_t(sizeof(ST));
+  return *reinterpret_cast<const ST *>(reinterpret_cast<const unsigned char *>(base + uniform) + boff);
 }
 template <class ST>
 __device__ __forceinline__ void stp(ST *base, uint64_t uniform, uint32_t lane, ST v) {
-  __builtin_nontemporal_store(v, (base + uniform) + lane);
+  const uint32_t boff = lane * uint32_t(sizeof(ST));
+  __builtin_nontemporal_store(v, reinterpret_cast<ST *>(reinterpret_cast<unsigned char *>(base + uniform) + boff));
 }
 
 // natural-index helpers for the batched kernel (cell = (z * ny + y) * nx + x inside a box)

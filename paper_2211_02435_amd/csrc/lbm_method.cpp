@@ -268,8 +268,8 @@ lbm_status validate(const lbm_params *p) {
   {
     uint64_t ps, zs, ys, elems;
     storage_strides(p, &ps, &zs, &ys, &elems);
-    if (double(zs) >= 4294967295.0)
-      return fail(LBM_EUNSUPPORTED, "one z-plane of the population storage must stay below 2^32 elements");
+    if (double(zs) * double(storage_bytes(p->storage)) >= 4294967295.0)
+      return fail(LBM_EUNSUPPORTED, "one z-plane of the population storage must stay below 4 GiB (32-bit lane offsets)");
   }
   if (p->nx > 2147483647 || p->ny > 2147483647 || p->nz > 2147483647) return fail(LBM_EINVAL, "dims too large");
   return LBM_OK;

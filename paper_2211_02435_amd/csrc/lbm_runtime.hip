@@ -40,6 +40,7 @@ namespace lbm {
 
 const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweep, sp, eq, reg, pat) }
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
+const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -118,6 +119,7 @@ struct lbm_ctx {
   int bx = 64, by = 4, swz = 0;
   bool vec = false;   // vectorised sweep (V cells per lane) where the shape allows it
   int lds = 0;        // dynamic LDS reserved per sweep block: caps resident blocks per CU
+  int transform = 0;  // LBM_TRANSFORM_CHIMERA or LBM_TRANSFORM_DENSE_MFMA (ablation)
   bool graphs = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
@@ -167,6 +169,28 @@ static hipError_t launch_sweep_t(const lbm_ctx *c, const void *fn, const void *s
   return hipLaunchKernel(fn, grid, dim3(c->bx, c->by), args, size_t(c->lds), c->stream);
 }
 
+// MFMA ablation: per-wave LDS of 27 x 65 compute values (F64: doubles, else floats)
+static int mfma_lds_bytes(const lbm_ctx *c) {
+  const int waves = (c->bx * c->by + 63) / 64;
+  return waves * 27 * 65 * (c->store == F64 ? 8 : 4);
+}
+
+template <class ST, class CT>
+static hipError_t launch_sweep_lds_t(const lbm_ctx *c, const void *fn, const void *src, void *dst, int lds) {
+  SweepArgs<ST, CT> a = make_sweep_args<ST, CT>(c, src, dst, false);
+  void *args[] = {&a};
+  const dim3 grid(unsigned(uint64_t(a.tiles_x) * uint64_t(a.tiles_y) * uint64_t(c->nz)));
+  return hipLaunchKernel(fn, grid, dim3(c->bx, c->by), args, size_t(lds), c->stream);
+}
+
+static hipError_t launch_sweep_lds(const lbm_ctx *c, const void *fn, const void *src, void *dst, int lds) {
+  switch (c->store) {
+    case F64: return launch_sweep_lds_t<double, double>(c, fn, src, dst, lds);
+    case F32: return launch_sweep_lds_t<float, float>(c, fn, src, dst, lds);
+    default: return launch_sweep_lds_t<_Float16, float>(c, fn, src, dst, lds);
+  }
+}
+
 static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src, void *dst, bool vec) {
   switch (c->store) {
     case F64: return launch_sweep_t<double, double>(c, fn, src, dst, vec);
@@ -192,10 +216,16 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     src = c->buf[0];
     dst = c->buf[0];
   }
-  const bool vec = c->vec && pat != AA_ODD && vec_ok(c, c->bx);
-  const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);
-  if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
-  HIPCHECK(launch_sweep(c, fn, src, dst, vec), "sweep launch");
+  if (c->transform == LBM_TRANSFORM_DENSE_MFMA && sp_override < 0) {
+    const void *fn = sweep_mfma_fn(c->s, c->store, sp, reg);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no MFMA ablation kernel for this method");
+    HIPCHECK(launch_sweep_lds(c, fn, src, dst, mfma_lds_bytes(c)), "sweep launch");
+  } else {
+    const bool vec = c->vec && pat != AA_ODD && vec_ok(c, c->bx);
+    const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
+    HIPCHECK(launch_sweep(c, fn, src, dst, vec), "sweep launch");
+  }
   if (c->pattern == LBM_STREAM_PULL) c->cur ^= 1;
   c->t += 1;
   return LBM_OK;
@@ -593,6 +623,7 @@ extern "C" lbm_status lbm_set_launch(lbm_ctx *c, int bx, int by, int swz) {
   c->by = by;
   c->swz = swz ? 1 : 0;
   if (c->vec && !vec_ok(c, bx)) c->vec = false;
+  if (c->transform == LBM_TRANSFORM_DENSE_MFMA && bx * by > 256) c->transform = LBM_TRANSFORM_CHIMERA;
   return LBM_OK;
 }
 
@@ -606,6 +637,23 @@ extern "C" lbm_status lbm_set_vectorized(lbm_ctx *c, int enable) {
 }
 
 extern "C" int lbm_get_vectorized(const lbm_ctx *c) { return c && c->vec ? 1 : 0; }
+
+extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (transform != LBM_TRANSFORM_CHIMERA && transform != LBM_TRANSFORM_DENSE_MFMA)
+    return fail(LBM_EINVAL, "transform out of range");
+  if (transform == LBM_TRANSFORM_DENSE_MFMA) {
+    if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL)
+      return fail(LBM_EUNSUPPORTED, "the MFMA ablation covers D3Q27, pull streaming, Maxwellian equilibrium");
+    if (c->bx * c->by > 256 || (c->bx * c->by) % 64 != 0)
+      return fail(LBM_EUNSUPPORTED, "the MFMA ablation needs blocks of 64..256 threads (whole waves)");
+  }
+  if (c->transform != transform) clear_graphs(c);
+  c->transform = transform;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_transform(const lbm_ctx *c) { return c ? c->transform : -1; }
 
 extern "C" lbm_status lbm_set_lds_reserve(lbm_ctx *c, int bytes) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;

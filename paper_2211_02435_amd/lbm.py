@@ -61,6 +61,8 @@ SIGNATURES = {
     "lbm_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     "lbm_set_vectorized": (c_int, [c_void_p, c_int]),
     "lbm_get_vectorized": (c_int, [c_void_p]),
+    "lbm_set_transform": (c_int, [c_void_p, c_int]),
+    "lbm_get_transform": (c_int, [c_void_p]),
     "lbm_set_lds_reserve": (c_int, [c_void_p, c_int]),
     "lbm_get_lds_reserve": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p]),
@@ -256,6 +258,12 @@ class Lattice:
 
     def lbm_get_vectorized(self):
         return bool(self.lib.lbm_get_vectorized(self.ctx))
+
+    def lbm_set_transform(self, transform):
+        check(self.lib.lbm_set_transform(self.ctx, {"chimera": 0, "dense_mfma": 1}[transform]))
+
+    def lbm_get_transform(self):
+        return {0: "chimera", 1: "dense_mfma"}[int(self.lib.lbm_get_transform(self.ctx))]
 
     def lbm_set_lds_reserve(self, nbytes):
         check(self.lib.lbm_set_lds_reserve(self.ctx, int(nbytes)))

@@ -343,3 +343,41 @@ def test_vectorized_fp64_matches_oracle():
     lat.lbm_set_populations(df0)
     lat.lbm_step(3)
     assert np.abs(lat.lbm_get_populations() - O.step(m, df0, 3)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
+@pytest.mark.parametrize("kind", ["reg", "gen"])
+def test_mfma_ablation_fp64_matches_oracle(space, kind):
+    """Dense M df / M^-1 dm* on the matrix cores (ablation) against the oracle, FP64, on a
+    ragged grid whose last tiles have idle lanes that still join the wave-wide products."""
+    dims = RAGGED3
+    om = _rates("D3Q27", kind, seed=7)
+    m = O.Method("D3Q27", space, om)
+    df0 = _noisy_state(m, dims, seed=13)
+    lat = _lattice("D3Q27", space, om, dims, storage="f64")
+    lat.lbm_set_launch(64, 4, 0)
+    lat.lbm_set_transform("dense_mfma")
+    assert lat.lbm_get_transform() == "dense_mfma"
+    lat.lbm_set_populations(df0)
+    lat.lbm_step(3)
+    err = np.abs(lat.lbm_get_populations() - O.step(m, df0, 3)).max()
+    print("MFMA ablation %s %s FP64: max|d df| = %.3e" % (space, kind, err))
+    assert err <= 1e-13
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-8), ("f16", 1e-2)])
+def test_mfma_ablation_close_to_chimera(storage, tol):
+    dims = (128, 9, 5)
+    om = _rates("D3Q27", "reg")
+    rho, u = W.tgv3d_fields(*dims, u0=0.05, period=16)
+    outs = []
+    for tr in ("chimera", "dense_mfma"):
+        lat = _lattice("D3Q27", "cumulant", om, dims, storage=storage)
+        lat.lbm_set_launch(128, 2, 0)
+        lat.lbm_set_transform(tr)
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_step(5)
+        outs.append(lat.lbm_get_populations())
+    err = np.abs(outs[0] - outs[1]).max()
+    print("MFMA vs Chimera %s: max|d df| = %.3e" % (storage, err))
+    assert err <= tol
