@@ -54,12 +54,26 @@ def workload_fields(name, cfg, n):
     return W.tgv3d_fields(n, u0=cfg["u0"]), (n, n, n)
 
 
-def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout, transform="chimera"):
+def workload_rates(cfg, general=False):
+    """Regularized rates of the workload; with general=True every rate of order >= 3 is 1.3
+    instead of 1, which selects the general (non-regularized) kernels."""
+    import oracle as O
+    om = O.regularized_rates(cfg["stencil"], cfg["omega_shear"])
+    if general:
+        st = O.stencil(cfg["stencil"])
+        for k, poly in enumerate(st.basis):
+            if sum(next(iter(poly))) >= 3:
+                om[k] = 1.3
+    return om
+
+
+def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout, transform="chimera",
+                general=False):
     """Run one box: init, autotune, warm-up, record the graph, time `steps` sweeps."""
     import oracle as O
     import torch
     stencil, space = cfg["stencil"], cfg["space"]
-    om = O.regularized_rates(stencil, cfg["omega_shear"])
+    om = workload_rates(cfg, general)
     q = O.stencil(stencil).q
     kw = {}
     if cfg.get("equilibrium") == "swe":
@@ -178,6 +192,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "planes", "rows"])
     ap.add_argument("--streaming", default="pull", choices=["pull", "aa"])
+    ap.add_argument("--rates", default="regularized", choices=["regularized", "general"],
+                    help="general: every rate of order >= 3 set to 1.3 (non-regularized kernels)")
     ap.add_argument("--transform", default="chimera", choices=["chimera", "dense_mfma"],
                     help="dense_mfma: the measured ablation of the raw-moment transform on MFMA")
     ap.add_argument("--cpu-size", type=int, default=32)
@@ -216,7 +232,8 @@ def main():
     runs, lats = {}, {}
     for st in storages:
         lat, res = measure_box(lbm, cfg, st, fields, dims, args.steps, args.warmup,
-                               not args.no_autotune, args.streaming, args.layout, args.transform)
+                               not args.no_autotune, args.streaming, args.layout, args.transform,
+                               args.rates == "general")
         runs[st], lats[st] = res, lat
         print("[bench] %s: %.0f MLUPS, %.1f GB/s" % (st, res["mlups"], res["achieved_GBps"]),
               file=sys.stderr, flush=True)
@@ -243,9 +260,9 @@ def main():
     r = runs[main_st]
     fields_desc = ("shallow water g 0.1, 16 Gaussian bumps" if name == "swe_d2q9_4096"
                    else "Taylor-Green u0 %.2f" % cfg["u0"])
-    workload = "%s %s %s periodic, %s, omega_s %.6f, other rates 1, %s" % (
+    workload = "%s %s %s periodic, %s, omega_s %.6f, %s, %s" % (
         cfg["stencil"], cfg["space"], "x".join(str(d) for d in dims), fields_desc, cfg["omega_shear"],
-        args.streaming)
+        "other rates 1" if args.rates == "regularized" else "orders >= 3 at 1.3, bulk 1", args.streaming)
     out = {
         "metric": ("MLUPS and % of HBM roofline, D3Q27 cumulant 512^3, FP32 vs FP64" if is_metric
                    else "MLUPS and % of HBM roofline, " + name),
@@ -262,14 +279,16 @@ def main():
         "data": "synthetic initial fields (Taylor-Green vortex / Gaussian water bumps)",
         "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
                    "layout": args.layout, "streaming": args.streaming, "transform": args.transform,
+                   "rates": args.rates,
                    "launch_bx_by_swizzle_vec_lds": r["launch_bx_by_swizzle_vec_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
                      "traffic": measured_traffic(name) if (n == cfg["dims"][0] and main_st == "f32"
                                                            and args.layout == "auto" and args.streaming == "pull"
-                                                           and args.transform == "chimera") else None,
-                     "kernel": "sweep_kernel<%s, %s, regularized, %s, %s>" % (cfg["stencil"], cfg["space"],
-                                                                              main_st, args.streaming),
+                                                           and args.transform == "chimera"
+                                                           and args.rates == "regularized") else None,
+                     "kernel": "sweep_kernel<%s, %s, %s, %s, %s>" % (cfg["stencil"], cfg["space"], args.rates,
+                                                                     main_st, args.streaming),
                      "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},
         "fp64": runs.get("f64") if main_st != "f64" else None,
         "velocity_rel_l2_vs_fp64": vel,

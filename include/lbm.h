@@ -101,7 +101,7 @@ typedef struct {
   int space;              /* lbm_space                                                        */
   int equilibrium;        /* lbm_equilibrium                                                  */
   int eq_form;            /* lbm_eq_form                                                      */
-  int zero_centered;      /* must be 1: populations are stored as df = f - f0 (sec. 2.1)      */
+  int zero_centered;      /* 1: store df = f - f0 (sec. 2.1); 0: store absolute f (Maxwellian) */
   const double *omegas;   /* host array of n_omegas rates, basis order above, each in [0, 2]  */
   int n_omegas;           /* == q                                                             */
   double gravity;         /* g > 0 for LBM_EQ_SHALLOW_WATER, ignored otherwise                */
@@ -125,8 +125,12 @@ lbm_status lbm_params_default(lbm_params *p);
  * LBM_EINVAL for bad enums, dims < 1, n_omegas != q, NULL omegas, non-finite or out-of-range
  * rates, gravity <= 0 with the shallow-water equilibrium.  LBM_EUNSUPPORTED for the
  * restrictions of sec. 3 (delta-equilibrium needs zero-centred storage; the cumulant space
- * admits no delta-equilibrium), absolute storage, D2Q9 with nz != 1, the shallow-water
- * equilibrium on a 3-D stencil or in cumulant space, non-periodic axes. */
+ * admits no delta-equilibrium), absolute storage with the shallow-water equilibrium, D2Q9 with
+ * nz != 1, the shallow-water equilibrium on a 3-D stencil or in cumulant space, non-periodic
+ * axes.
+ * Absolute storage keeps f = df + w in the buffers (the "absolute" storage format of the
+ * paper, used for the round-off plateau study of sec. 5.1): every sweep subtracts w after
+ * loading and adds it back before storing, so f is rounded to the storage precision. */
 lbm_status lbm_validate(const lbm_params *p);
 
 /* Bytes of device population storage the parameter set needs in total (both arrays for

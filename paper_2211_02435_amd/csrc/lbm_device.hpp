@@ -81,6 +81,13 @@ struct Lat {
   __host__ __device__ static constexpr int gidx(int i) {
     return (c(i, 0) + 1) + 3 * (c(i, 1) + 1) + (D == 3 ? 9 * (c(i, 2) + 1) : 0);
   }
+  // lattice weight of velocity i (background f0 = w of the Maxwellian equilibrium, sec. 2.4)
+  __host__ __device__ static constexpr double w(int i) {
+    const int n = (c(i, 0) != 0) + (c(i, 1) != 0) + (c(i, 2) != 0);
+    if (S == D2Q9) return n == 0 ? 4.0 / 9.0 : (n == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+    if (S == D3Q19) return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    return n == 0 ? 8.0 / 27.0 : (n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
+  }
   // is the monomial x^a y^b z^c part of the stencil's moment set?
   __host__ __device__ static constexpr bool has_mono(int a, int b, int cc) {
     return S == D2Q9 ? (cc == 0) : (S == D3Q19 ? (a == 0 || b == 0 || cc == 0) : true);

@@ -46,6 +46,7 @@ struct SweepArgs {
   Strides L;
   int tiles_x, tiles_y;
   int swizzle;       // nonzero: consecutive tiles on one XCD
+  int absolute;      // nonzero: buffers hold absolute populations f = df + w
   CT grav;
   Relax<CT> R;
 };
@@ -172,7 +173,9 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     }
   });
 
+  if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
   collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+  if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
 
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -273,7 +276,11 @@ __global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
     }
   });
 
-  sfor<V>([&](auto K) { collide<S, SP, EQ, REG, CT>(g[K], a.R, a.grav); });
+  sfor<V>([&](auto K) {
+    if (a.absolute) sfor<L::Q>([&](auto I) { g[K][L::gidx(I)] -= CT(L::w(I)); });
+    collide<S, SP, EQ, REG, CT>(g[K], a.R, a.grav);
+    if (a.absolute) sfor<L::Q>([&](auto I) { g[K][L::gidx(I)] += CT(L::w(I)); });
+  });
 
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
@@ -302,6 +309,7 @@ struct FieldArgs {
   double *pop;            // export (out) / import (in): df[i * ncells + c], FP64
   double *partials;       // diagnostics: 6 per block
   int i0, i1;             // population range of export / import (chunking)
+  int absolute;           // nonzero: buffers hold absolute populations f = df + w
 };
 
 // storage address (uniform part, lane part) of the canonical df_i(x) for layout GM
@@ -334,7 +342,7 @@ __device__ __forceinline__ void gather_canon(const FieldArgs &a, const CellPos &
     uint64_t uni;
     uint32_t lane;
     canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
-    f[i] = double(ldp(buf, uni, lane));
+    f[i] = double(ldp(buf, uni, lane)) - (a.absolute ? L::w(i) : 0.0);
   });
 }
 
@@ -356,7 +364,7 @@ __global__ void __launch_bounds__(256) init_kernel(FieldArgs a) {
     uint64_t uni;
     uint32_t lane;
     canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
-    stp(buf, uni, lane, ST(g[L::gidx(i)]));
+    stp(buf, uni, lane, ST(g[L::gidx(i)] + (a.absolute ? L::w(i) : 0.0)));
   });
 }
 
@@ -374,7 +382,7 @@ __global__ void __launch_bounds__(256) export_kernel(FieldArgs a) {
       uint64_t uni;
       uint32_t lane;
       canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
-      a.pop[size_t(i - a.i0) * a.ncells + self] = double(ldp(buf, uni, lane));
+      a.pop[size_t(i - a.i0) * a.ncells + self] = double(ldp(buf, uni, lane)) - (a.absolute ? L::w(i) : 0.0);
     }
   });
 }
@@ -393,7 +401,7 @@ __global__ void __launch_bounds__(256) import_kernel(FieldArgs a) {
       uint64_t uni;
       uint32_t lane;
       canon_addr<S, GM>(nb, a.L, i, L::c(i, 0), L::c(i, 1), L::c(i, 2), uni, lane);
-      stp(buf, uni, lane, ST(a.pop[size_t(i - a.i0) * a.ncells + self]));
+      stp(buf, uni, lane, ST(a.pop[size_t(i - a.i0) * a.ncells + self] + (a.absolute ? L::w(i) : 0.0)));
     }
   });
 }

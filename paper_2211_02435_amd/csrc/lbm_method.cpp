@@ -249,7 +249,8 @@ lbm_status validate(const lbm_params *p) {
   if (!p->zero_centered) {
     if (p->eq_form == LBM_EQFORM_DELTA)
       return fail(LBM_EUNSUPPORTED, "the delta-equilibrium requires zero-centred storage");
-    return fail(LBM_EUNSUPPORTED, "absolute population storage is not implemented (zero_centered must be 1)");
+    if (p->equilibrium != LBM_EQ_MAXWELLIAN)
+      return fail(LBM_EUNSUPPORTED, "absolute population storage is implemented for the Maxwellian equilibrium");
   }
   if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
     return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");

@@ -136,9 +136,11 @@ __global__ void __launch_bounds__(256) sweep_mfma_kernel(SweepArgs<ST, CT> a) {
       g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     });
   }
+  if (a.absolute && valid) sfor<27>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
   wave_dense27<false, CT>(g, lds, lane);
   collide_moments<D3Q27, SP, MAXWELL, REG, CT>(g, a.R, CT(0));
   wave_dense27<true, CT>(g, lds, lane);
+  if (a.absolute) sfor<27>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
   if (valid) {
     sfor<27>([&](auto I) {
       constexpr int i = decltype(I)::value;

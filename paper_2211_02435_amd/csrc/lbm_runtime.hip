@@ -148,6 +148,7 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.tiles_x = (c->nx + cells_x - 1) / cells_x;
   a.tiles_y = (c->ny + c->by - 1) / c->by;
   a.swizzle = c->swz;
+  a.absolute = c->p.zero_centered ? 0 : 1;
   a.grav = CT(c->p.gravity);
   for (int j = 0; j < 6; ++j)
     for (int k = 0; k < 6; ++k) a.R.b2[j][k] = CT(c->R.b2[j][k]);
@@ -242,6 +243,7 @@ static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
   std::memset(&a, 0, sizeof(a));
   a.buf = buf;
   a.L = c->L;
+  a.absolute = c->p.zero_centered ? 0 : 1;
   a.ncells = c->ncells;
   a.nx = c->nx;
   a.ny = c->ny;
@@ -1029,6 +1031,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   if (common->stencil == LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the batched ensemble is three-dimensional");
   if (common->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the pull pattern");
   if (common->equilibrium != LBM_EQ_MAXWELLIAN) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the Maxwellian");
+  if (!common->zero_centered) return fail(LBM_EUNSUPPORTED, "the batched ensemble stores zero-centred populations");
   lbm_batch *b = new lbm_batch();
   b->p = *common;
   b->s = common->stencil;

@@ -160,7 +160,8 @@ class Lattice:
     (torch_buffers=True) or by the library.  Work runs on a torch stream of default priority."""
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
-                 equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto"):
+                 equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto",
+                 zero_centered=True):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
@@ -168,7 +169,7 @@ class Lattice:
         self.dims = tuple(int(v) for v in dims)
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
-                        layout=layout)
+                        zero_centered=1 if zero_centered else 0, layout=layout)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []

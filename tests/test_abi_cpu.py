@@ -49,6 +49,12 @@ def _p(**kw):
     return lbm.make_params(st, kw.pop("space", "cumulant"), om, dims, **kw)
 
 
+def test_absolute_storage_accepted_for_the_maxwellian():
+    assert lbm.lbm_validate(_p(space="raw", zero_centered=0)) == 0
+    assert lbm.lbm_validate(_p(space="cumulant", zero_centered=0)) == 0
+    assert lbm.lbm_validate(_p(space="raw", zero_centered=0, eq_form="delta")) == lbm.LBM_EUNSUPPORTED
+
+
 def test_valid_parameter_sets():
     for st in ("D2Q9", "D3Q19", "D3Q27"):
         for sp in ("raw", "central", "cumulant"):
@@ -69,7 +75,7 @@ def test_valid_parameter_sets():
     (dict(stencil="D2Q9", space="central", equilibrium="swe", gravity=0.0), lbm.LBM_EINVAL),
     (dict(space="cumulant", eq_form="delta"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", eq_form="delta", zero_centered=0), lbm.LBM_EUNSUPPORTED),
-    (dict(space="raw", zero_centered=0), lbm.LBM_EUNSUPPORTED),
+    (dict(stencil="D2Q9", space="central", equilibrium="swe", gravity=0.1, zero_centered=0), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D2Q9", dims=(8, 8, 2)), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D3Q27", space="central", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D2Q9", space="cumulant", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),

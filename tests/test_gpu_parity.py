@@ -381,3 +381,20 @@ def test_mfma_ablation_close_to_chimera(storage, tol):
     err = np.abs(outs[0] - outs[1]).max()
     print("MFMA vs Chimera %s: max|d df| = %.3e" % (storage, err))
     assert err <= tol
+
+
+@pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_absolute_storage_fp64_matches_oracle(space, streaming):
+    """Absolute storage (f = df + w in the buffers, eq. MrtUpdateGeneral's storage format):
+    FP64 populations after 5 steps against the oracle."""
+    dims = RAGGED3
+    om = _rates("D3Q27", "gen", seed=8)
+    m = O.Method("D3Q27", space, om)
+    df0 = _noisy_state(m, dims, seed=21)
+    lat = _lattice("D3Q27", space, om, dims, storage="f64", streaming=streaming, zero_centered=False)
+    lat.lbm_set_populations(df0)
+    lat.lbm_step(5)
+    err = np.abs(lat.lbm_get_populations() - O.step(m, df0, 5)).max()
+    print("absolute storage %s %s: max|d df| = %.3e" % (space, streaming, err))
+    assert err <= 1e-13
