@@ -77,10 +77,14 @@ typedef enum {
 } lbm_status;
 
 typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_stencil;
-typedef enum { LBM_SPACE_RAW = 0, LBM_SPACE_CENTRAL = 1, LBM_SPACE_CUMULANT = 2 } lbm_space;
+/* SRT: the single-relaxation-time method in population space (eq. MrtUpdateGeneral with the
+ * identity transform and S = omega I, the SRT row of the method table of sec. 4.3); its
+ * equilibrium is the second-order polynomial f_eq_i = w_i rho (1 + 3 xi.u + 9/2 (xi.u)^2
+ * - 3/2 u.u), and every rate of a non-conserved polynomial must be the same omega. */
+typedef enum { LBM_SPACE_RAW = 0, LBM_SPACE_CENTRAL = 1, LBM_SPACE_CUMULANT = 2, LBM_SPACE_SRT = 3 } lbm_space;
 typedef enum { LBM_EQ_MAXWELLIAN = 0, LBM_EQ_SHALLOW_WATER = 1 } lbm_equilibrium;
-/* DEFAULT resolves to DELTA for raw and central moments with the Maxwellian, to ABSOLUTE for
- * cumulants and for the shallow-water equilibrium. */
+/* DEFAULT resolves to DELTA for raw and central moments and SRT with the Maxwellian, to
+ * ABSOLUTE for cumulants and for the shallow-water equilibrium. */
 typedef enum { LBM_EQFORM_DEFAULT = 0, LBM_EQFORM_ABSOLUTE = 1, LBM_EQFORM_DELTA = 2 } lbm_eq_form;
 /* Storage precision of the populations.  Compute precision is FP64 for F64 storage and FP32
  * for F32 and F16 storage.  Initialisation and every reader compute in FP64. */
@@ -89,6 +93,18 @@ typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_sto
  * (even steps read and write the cell's own slots, odd steps read from x - xi_i and write to
  * x + xi_i); sec. 4.4. */
 typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1 } lbm_streaming;
+
+/* How the collision's arithmetic is organised.  DEVIATION: every intermediate is a deviation
+ * from the background (raw, central and cumulant moments of df, the equilibrium deviation
+ * expanded so that no background value is subtracted), whatever the storage format and
+ * eq_form; in exact arithmetic it equals each admissible form of sec. 2.2.  LITERAL: the form
+ * is evaluated as written, for the round-off study of sec. 5.1: absolute storage ->
+ * eq. MrtUpdateGeneral on absolute populations and moments; zero-centred storage with the
+ * delta-equilibrium -> eq. MrtUpdateGeneralDeviationOnly with dq_eq = q_eq - T(f0) formed by
+ * subtraction; zero-centred storage with the absolute equilibrium ->
+ * eq. MrtUpdateAbsoluteFromZeroCentered (q = T(df + f0), df* = T^-1(q*) - f0).  LITERAL
+ * covers D2Q9 and D3Q27, F64 and F32 storage, pull streaming, the Maxwellian equilibrium. */
+typedef enum { LBM_ARITH_DEVIATION = 0, LBM_ARITH_LITERAL = 1 } lbm_arithmetic;
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
@@ -113,12 +129,14 @@ typedef struct {
   size_t buffer_bytes;    /* each >= lbm_required_bytes / nbuffers; NULL -> library allocates */
   void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
   int layout;             /* lbm_layout of the device population buffers                      */
+  int arithmetic;         /* lbm_arithmetic of the collision                                  */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fill *p with defaults: D3Q27, cumulant, Maxwellian, DEFAULT form, zero-centred, FP32, pull,
- * periodic, 1x1x1, no rates, AUTO layout.  Always succeeds for non-NULL p. */
+ * periodic, 1x1x1, no rates, AUTO layout, DEVIATION arithmetic.  Always succeeds for
+ * non-NULL p. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Validate a parameter set without touching any device (pure host code).
@@ -127,10 +145,12 @@ lbm_status lbm_params_default(lbm_params *p);
  * restrictions of sec. 3 (delta-equilibrium needs zero-centred storage; the cumulant space
  * admits no delta-equilibrium), absolute storage with the shallow-water equilibrium, D2Q9 with
  * nz != 1, the shallow-water equilibrium on a 3-D stencil or in cumulant space, non-periodic
- * axes.
+ * axes, SRT with unequal rates (EINVAL) or the shallow-water equilibrium, LITERAL arithmetic
+ * outside D2Q9/D3Q27, F64/F32, pull, Maxwellian.
  * Absolute storage keeps f = df + w in the buffers (the "absolute" storage format of the
- * paper, used for the round-off plateau study of sec. 5.1): every sweep subtracts w after
- * loading and adds it back before storing, so f is rounded to the storage precision. */
+ * paper, used for the round-off plateau study of sec. 5.1).  With DEVIATION arithmetic every
+ * sweep subtracts w after loading and adds it back before storing, so only the storage
+ * rounds f; with LITERAL arithmetic the whole collision runs on absolute values. */
 lbm_status lbm_validate(const lbm_params *p);
 
 /* Bytes of device population storage the parameter set needs in total (both arrays for

@@ -28,6 +28,12 @@ tests/test_oracle_*.py check it against something other than itself):
         pin: the three forms agree, equilibrium is a fixed point, per-cell conservation,
              all rates 0 -> identity, all rates 1 -> equilibrium, raw space with equal
              rates -> BGK, Taylor-Green decay exp(-2 nu k^2 t) (sec. 5.1)
+  srt_equilibrium / 'srt'    single relaxation time (eq. MrtUpdateGeneral with the identity
+                             transform and S = omega I; the SRT method of sec. 4.3 and 5.1)
+                             with the second-order polynomial equilibrium
+        pin: moments of orders 0..2 are rho, rho u, rho (cs2 delta + u u) on every stencil;
+             on the tensor-product stencils D2Q9 / D3Q27 one SRT collision equals the
+             raw-moment collision with all rates omega (moment-space BGK)
   stream                     eq. LbUpdateScheme (sec. 2.1), periodic
         pin: impulse moves by xi_i; N steps of pure streaming on an N-periodic box return
              the initial state
@@ -316,6 +322,14 @@ def cumulant_maxwellian(st, rho, u):
     return out
 
 
+def srt_equilibrium(st, rho, u):
+    """Second-order polynomial equilibrium of the SRT method (sec. 2.4 expanded to second order
+    in u): f_eq_i = w_i rho (1 + xi.u / cs2 + (xi.u)^2 / (2 cs2^2) - u.u / (2 cs2))."""
+    xu = u @ st.xi.T.astype(np.float64)  # (n, q)
+    uu = (u * u).sum(axis=1)[:, None]
+    return st.w[None, :] * rho[:, None] * (1.0 + xu / CS2 + xu * xu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2))
+
+
 def swe_equilibrium(st, h, u, g):
     """Discrete shallow-water equilibrium of Zhou on D2Q9 (sec. 5.2, eq.
     DiscreteShallowWaterEquilibrium and the listing).  Reading: the last term of f_i,
@@ -339,8 +353,9 @@ def swe_equilibrium(st, h, u, g):
 class Method:
     """stencil, collision space, one relaxation rate per basis polynomial, equilibrium.
 
-    space: 'raw' | 'central' | 'cumulant'; equilibrium: 'maxwellian' | 'swe'.
-    Rates of the conserved polynomials (1, x, y, z) are ignored (pass-through)."""
+    space: 'raw' | 'central' | 'cumulant' | 'srt'; equilibrium: 'maxwellian' | 'swe'.
+    Rates of the conserved polynomials (1, x, y, z) are ignored (pass-through).  'srt' works
+    on the populations themselves with one rate, the common value of the non-conserved rates."""
 
     def __init__(self, stencil_name, space, omegas, equilibrium="maxwellian", gravity=None):
         self.st = stencil(stencil_name)
@@ -349,6 +364,10 @@ class Method:
         assert self.omegas.shape == (self.st.q,)
         self.equilibrium = equilibrium
         self.gravity = gravity
+        if space == "srt":
+            assert equilibrium == "maxwellian"
+            rest = self.omegas[self.st.d + 1:]
+            assert np.all(rest == rest[0]), "SRT needs one rate"
         if equilibrium == "swe":
             assert stencil_name == "D2Q9" and space in ("raw", "central")
             # background: the rest state h = 1, u = 0 of the discrete equilibrium
@@ -359,6 +378,8 @@ class Method:
     # --- transforms T and T^-1 in monomial form ---------------------------------------
     def forward(self, f, rho, u):
         st = self.st
+        if self.space == "srt":
+            return np.array(f, dtype=np.float64)
         if self.space == "raw":
             return f @ st.M.T
         kappa = np.einsum("nji,ni->nj", central_matrix(st, u), f)
@@ -368,6 +389,8 @@ class Method:
 
     def backward(self, qm, rho, u):
         st = self.st
+        if self.space == "srt":
+            return qm
         if self.space == "raw":
             return np.linalg.solve(st.M, qm.T).T
         if self.space == "cumulant":
@@ -379,6 +402,8 @@ class Method:
         if self.equilibrium == "swe":
             feq = swe_equilibrium(st, rho, u, self.gravity)
             return self.forward(feq, rho, u)
+        if self.space == "srt":
+            return srt_equilibrium(st, rho, u)
         if self.space == "raw":
             return raw_maxwellian_truncated(st, rho, u)
         if self.space == "central":
@@ -386,8 +411,12 @@ class Method:
         return cumulant_maxwellian(st, rho, u)
 
     def relax(self, q_mono, q_eq_mono):
-        """q = P q_mono; q* = q + S (q_eq - q) on non-conserved rows; back to monomials."""
+        """q = P q_mono; q* = q + S (q_eq - q) on non-conserved rows; back to monomials.
+        SRT: q are the populations, q* = q + omega (q_eq - q) on every one of them."""
         st = self.st
+        if self.space == "srt":
+            om = self.omegas[st.d + 1]
+            return q_mono + om * (q_eq_mono - q_mono)
         q = q_mono @ st.P.T
         qe = q_eq_mono @ st.P.T
         om = self.omegas.copy()

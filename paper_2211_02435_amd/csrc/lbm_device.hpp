@@ -33,7 +33,9 @@
 namespace lbm {
 
 enum StencilId { D2Q9 = 0, D3Q19 = 1, D3Q27 = 2 };
-enum SpaceId { RAW = 0, CENTRAL = 1, CUMULANT = 2, IDENTITY = 3 };
+// SRT: single relaxation time in population space (eq. MrtUpdateGeneral with T = identity
+// and S = omega I); IDENTITY: streaming only (no collision)
+enum SpaceId { RAW = 0, CENTRAL = 1, CUMULANT = 2, IDENTITY = 3, SRT = 4 };
 enum EqId { MAXWELL = 0, SWE = 1 };
 // PULL: gather from x - xi.  AA_EVEN: own slots, write to the opposite slot.
 // AA_ODD: read opposite slot at x - xi, write own slot at x + xi.
@@ -495,11 +497,62 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Single relaxation time in population space.  The second-order polynomial equilibrium
+//   f_eq_i = w_i rho (1 + xi.u / cs2 + (xi.u)^2 / (2 cs4) - u.u / (2 cs2))
+// in deviation form about f0 = w:
+//   df_eq_i = w_i (drho + rho (3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u)),
+// relaxed as df* = df_eq + (1 - omega)(df - df_eq); 1 - omega arrives as R.b2[0][0].
+// ---------------------------------------------------------------------------------------
+template <int S, class T>
+LBM_HD void srt_feq_dev(T *feq, T drho, T rho, const T *u) {
+  using L = Lat<S>;
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+    T xu = T(0);
+    if constexpr (cx != 0) xu = cx > 0 ? xu + u[0] : xu - u[0];
+    if constexpr (cy != 0) xu = cy > 0 ? xu + u[1] : xu - u[1];
+    if constexpr (cz != 0) xu = cz > 0 ? xu + u[2] : xu - u[2];
+    const T poly = T(3) * xu + T(4.5) * xu * xu - T(1.5) * uu;
+    feq[L::gidx(i)] = T(L::w(i)) * (drho + rho * poly);
+  });
+}
+
+template <int S, class T>
+LBM_HD void collide_srt(T *g, const Relax<T> &R) {
+  using L = Lat<S>;
+  T drho = T(0), j[3] = {T(0), T(0), T(0)};
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    const T v = g[L::gidx(i)];
+    drho += v;
+    sfor<3>([&](auto Dd) {
+      constexpr int d = decltype(Dd)::value;
+      if constexpr (L::c(i, d) > 0) j[d] += v;
+      else if constexpr (L::c(i, d) < 0) j[d] -= v;
+    });
+  });
+  const T rho = T(1) + drho;
+  const T rinv = T(1) / rho;
+  const T u[3] = {j[0] * rinv, j[1] * rinv, j[2] * rinv};
+  T feq[Lat<S>::G];
+  srt_feq_dev<S>(feq, drho, rho, u);
+  const T b = R.b2[0][0];
+  sfor<L::Q>([&](auto I) {
+    constexpr int gi = L::gidx(decltype(I)::value);
+    g[gi] = fma(b, g[gi] - feq[gi], feq[gi]);
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // the collision: g holds df (grid order, missing velocities zero) and receives df*
 // ---------------------------------------------------------------------------------------
 template <int S, int SP, int EQ, bool REG, class T>
 LBM_HD void collide(T *g, const Relax<T> &R, T grav) {
-  if constexpr (SP != IDENTITY) {
+  if constexpr (SP == SRT) {
+    collide_srt<S>(g, R);
+  } else if constexpr (SP != IDENTITY) {
     chimera_forward<S>(g);
     collide_moments<S, SP, EQ, REG, T>(g, R, grav);
     chimera_inverse<S>(g);
@@ -513,6 +566,9 @@ LBM_HD void equilibrium_dev(T *g, T drho, const T *u, T grav) {
   const T rho = T(1) + drho;
   if constexpr (EQ == SWE) {
     swe_feq_dev(g, drho, rho, u[0], u[1], grav);
+  } else if constexpr (SP == SRT) {
+    sfor<G>([&](auto E) { g[E] = T(0); });
+    srt_feq_dev<S>(g, drho, rho, u);
   } else {
     T uu[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
     sfor<G>([&](auto E) {

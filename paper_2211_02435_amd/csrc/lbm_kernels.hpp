@@ -47,6 +47,8 @@ struct SweepArgs {
   int tiles_x, tiles_y;
   int swizzle;       // nonzero: consecutive tiles on one XCD
   int absolute;      // nonzero: buffers hold absolute populations f = df + w
+  int bx, by;        // block shape (threads along x, rows along y)
+  const uint2 *tile_table;  // per block: (tx | ty << 16, tz), XCD order applied; or null
   CT grav;
   Relax<CT> R;
 };
@@ -76,6 +78,32 @@ __device__ __forceinline__ CellPos tile_cell(int nx, int ny, int tiles_x, int ti
   p.y = int(ty * blockDim.y + threadIdx.y);
   p.z = int(tz);
   p.valid = p.x < nx && p.y < ny;
+  return p;
+}
+
+// tile of this block from the host-built table (no divisions on the device), else computed
+template <class A>
+__device__ __forceinline__ CellPos tile_cell_args(const A &a, int cells_per_lane) {
+  uint32_t tx, ty, tz;
+  if (a.tile_table) {
+    const uint2 t = a.tile_table[blockIdx.x];
+    tx = t.x & 0xffffu;
+    ty = t.x >> 16;
+    tz = t.y;
+  } else {
+    uint32_t tile = blockIdx.x;
+    if (a.swizzle) tile = xcd_tile(blockIdx.x, gridDim.x);
+    const uint32_t per_plane = uint32_t(a.tiles_x) * uint32_t(a.tiles_y);
+    tz = tile / per_plane;
+    const uint32_t r = tile - tz * per_plane;
+    ty = r / uint32_t(a.tiles_x);
+    tx = r - ty * uint32_t(a.tiles_x);
+  }
+  CellPos p;
+  p.x = int((tx * uint32_t(a.bx) + threadIdx.x) * uint32_t(cells_per_lane));
+  p.y = int(ty * uint32_t(a.by) + threadIdx.y);
+  p.z = int(tz);
+  p.valid = p.x < a.nx && p.y < a.ny;
   return p;
 }
 
@@ -155,7 +183,7 @@ struct NbrNat {
 template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
   using L = Lat<S>;
-  const CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, a.swizzle);
+  const CellPos p = tile_cell_args(a, 1);
   if (!p.valid) return;
   const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
 
@@ -165,11 +193,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     if constexpr (PAT == PULL) {
-      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     } else if constexpr (PAT == AA_EVEN) {
-      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1)));
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
     } else {
-      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(L::opp(i)) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     }
   });
 
@@ -182,11 +210,11 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     const ST v = ST(g[L::gidx(i)]);
     if constexpr (PAT == PULL) {
-      stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
+      stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else if constexpr (PAT == AA_EVEN) {
-      stp(a.dst, uint64_t(L::opp(i)) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
+      stp(a.dst, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else {
-      stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
+      stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
     }
   });
 }
@@ -226,16 +254,8 @@ __global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
   constexpr int V = VecWidth<ST>::V;
   using VT = typename VecOf<ST, V>::T;
   static_assert(PAT == PULL || PAT == AA_EVEN, "vectorised sweep: pull and AA even steps");
-  uint32_t tile = blockIdx.x;
-  if (a.swizzle) tile = xcd_tile(blockIdx.x, gridDim.x);
-  const uint32_t per_plane = uint32_t(a.tiles_x) * uint32_t(a.tiles_y);
-  const uint32_t tz = tile / per_plane;
-  const uint32_t r = tile - tz * per_plane;
-  const uint32_t ty = r / uint32_t(a.tiles_x);
-  const uint32_t tx = r - ty * uint32_t(a.tiles_x);
-  const int x0 = int((tx * blockDim.x + threadIdx.x) * V);
-  const int y = int(ty * blockDim.y + threadIdx.y);
-  const int z = int(tz);
+  const CellPos pc = tile_cell_args(a, V);
+  const int x0 = pc.x, y = pc.y, z = pc.z;
   if (y >= a.ny) return;  // whole waves (blockDim.x is a multiple of 64)
   const Nbr<L::D> nb(x0, y, z, a.nx, a.ny, a.nz, a.L);
   const uint32_t lane_id = threadIdx.x & 63u;
@@ -251,10 +271,10 @@ __global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
     uint64_t uni;
     uint32_t row;
     if constexpr (PAT == PULL) {
-      uni = uint64_t(i) * a.L.ps + nb.zpart(cz, -1);
+      uni = (uint64_t(i) * a.L.ps) + nb.zpart(cz, -1);
       row = nb.yoff[1 - cy];
     } else {
-      uni = uint64_t(i) * a.L.ps + nb.zpart(0, 1);
+      uni = (uint64_t(i) * a.L.ps) + nb.zpart(0, 1);
       row = nb.yoff[1];
     }
     const ST *rp = a.src + uni + row;
@@ -287,7 +307,7 @@ __global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
     constexpr int slot = PAT == PULL ? i : L::opp(i);
     VT o;
     sfor<V>([&](auto K) { constexpr int k = decltype(K)::value; o[k] = ST(g[k][L::gidx(i)]); });
-    ST *dp = a.dst + (uint64_t(slot) * a.L.ps + nb.zpart(0, 1)) + nb.yoff[1];
+    ST *dp = a.dst + ((uint64_t(slot) * a.L.ps) + nb.zpart(0, 1)) + nb.yoff[1];
     __builtin_nontemporal_store(o, reinterpret_cast<VT *>(dp + x0));
   });
 }

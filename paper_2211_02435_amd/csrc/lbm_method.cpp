@@ -61,6 +61,13 @@ void storage_strides(const lbm_params *p, uint64_t *ps, uint64_t *zs, uint64_t *
   }
 }
 
+int internal_space(int public_space) { return public_space == LBM_SPACE_SRT ? kSpaceSrt : public_space; }
+
+int literal_form(const lbm_params *p) {
+  if (!p->zero_centered) return kLitA;
+  return resolve_eq_form(p) == LBM_EQFORM_DELTA ? kLitB : kLitC;
+}
+
 int resolve_eq_form(const lbm_params *p) {
   if (p->eq_form != LBM_EQFORM_DEFAULT) return p->eq_form;
   if (p->space == LBM_SPACE_CUMULANT || p->equilibrium == LBM_EQ_SHALLOW_WATER) return LBM_EQFORM_ABSOLUTE;
@@ -227,7 +234,9 @@ lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
 lbm_status validate(const lbm_params *p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->stencil < LBM_D2Q9 || p->stencil > LBM_D3Q27) return fail(LBM_EINVAL, "stencil out of range");
-  if (p->space < LBM_SPACE_RAW || p->space > LBM_SPACE_CUMULANT) return fail(LBM_EINVAL, "space out of range");
+  if (p->space < LBM_SPACE_RAW || p->space > LBM_SPACE_SRT) return fail(LBM_EINVAL, "space out of range");
+  if (p->arithmetic < LBM_ARITH_DEVIATION || p->arithmetic > LBM_ARITH_LITERAL)
+    return fail(LBM_EINVAL, "arithmetic out of range");
   if (p->equilibrium < LBM_EQ_MAXWELLIAN || p->equilibrium > LBM_EQ_SHALLOW_WATER)
     return fail(LBM_EINVAL, "equilibrium out of range");
   if (p->eq_form < LBM_EQFORM_DEFAULT || p->eq_form > LBM_EQFORM_DELTA) return fail(LBM_EINVAL, "eq_form out of range");
@@ -255,6 +264,21 @@ lbm_status validate(const lbm_params *p) {
   if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
     return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");
   if (p->stencil == LBM_D2Q9 && p->nz != 1) return fail(LBM_EUNSUPPORTED, "D2Q9 requires nz == 1");
+  if (p->space == LBM_SPACE_SRT) {
+    if (p->equilibrium != LBM_EQ_MAXWELLIAN)
+      return fail(LBM_EUNSUPPORTED, "SRT is implemented with the Maxwellian (polynomial) equilibrium");
+    for (int i = stencil_d(p->stencil) + 2; i < q; ++i)
+      if (p->omegas[i] != p->omegas[stencil_d(p->stencil) + 1])
+        return fail(LBM_EINVAL, "SRT needs one rate: every non-conserved rate must be equal");
+  }
+  if (p->arithmetic == LBM_ARITH_LITERAL) {
+    if (p->stencil != LBM_D2Q9 && p->stencil != LBM_D3Q27)
+      return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for D2Q9 and D3Q27");
+    if (p->storage == LBM_STORE_F16) return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic needs F64 or F32 storage");
+    if (p->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic runs with pull streaming");
+    if (p->equilibrium != LBM_EQ_MAXWELLIAN)
+      return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for the Maxwellian equilibrium");
+  }
   if (p->equilibrium == LBM_EQ_SHALLOW_WATER) {
     if (p->stencil != LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the shallow-water equilibrium is two-dimensional (D2Q9)");
     if (p->space == LBM_SPACE_CUMULANT)
@@ -287,6 +311,7 @@ extern "C" lbm_status lbm_params_default(lbm_params *p) {
   p->space = LBM_SPACE_CUMULANT;
   p->equilibrium = LBM_EQ_MAXWELLIAN;
   p->eq_form = LBM_EQFORM_DEFAULT;
+  p->arithmetic = LBM_ARITH_DEVIATION;
   p->zero_centered = 1;
   p->nx = p->ny = p->nz = 1;
   p->periodic[0] = p->periodic[1] = p->periodic[2] = 1;

@@ -25,6 +25,13 @@ int stencil_q(int s);
 int stencil_d(int s);
 size_t storage_bytes(int st);
 int resolve_eq_form(const lbm_params *p);
+// kernel-side identifiers (the device headers' SpaceId::SRT and LiteralForm)
+constexpr int kSpaceSrt = 4;
+constexpr int kLitA = 0, kLitB = 1, kLitC = 2;
+// kernel space id of a public lbm_space
+int internal_space(int public_space);
+// LITERAL arithmetic: which form of sec. 2.2 the parameter set selects (kLitA/B/C)
+int literal_form(const lbm_params *p);
 size_t plane_elems(const lbm_params *p);
 int resolve_layout(const lbm_params *p);
 void storage_strides(const lbm_params *p, uint64_t *ps, uint64_t *zs, uint64_t *ys, uint64_t *elems);

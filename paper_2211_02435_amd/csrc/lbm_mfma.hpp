@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) sweep_mfma_kernel(SweepArgs<ST, CT> a) {
   const int tid = threadIdx.y * blockDim.x + threadIdx.x;
   const int lane = tid & 63;
   CT *lds = reinterpret_cast<CT *>(lds_raw) + (tid >> 6) * (MFMA_ROWS * MFMA_LDS_STRIDE);
-  CellPos p = tile_cell(a.nx, a.ny, a.tiles_x, a.tiles_y, a.swizzle);
+  CellPos p = tile_cell_args(a, 1);
   // lanes outside the box still take part in the wave-wide products (with zero input)
   const bool valid = p.valid;
   if (!valid) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) sweep_mfma_kernel(SweepArgs<ST, CT> a) {
     sfor<27>([&](auto I) {
       constexpr int i = decltype(I)::value;
       constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
-      g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     });
   }
   if (a.absolute && valid) sfor<27>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
@@ -144,7 +144,7 @@ __global__ void __launch_bounds__(256) sweep_mfma_kernel(SweepArgs<ST, CT> a) {
   if (valid) {
     sfor<27>([&](auto I) {
       constexpr int i = decltype(I)::value;
-      stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), ST(g[L::gidx(i)]));
+      stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), ST(g[L::gidx(i)]));
     });
   }
 }

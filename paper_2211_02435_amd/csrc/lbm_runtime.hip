@@ -17,7 +17,11 @@
 #include "../../include/lbm.h"
 #include "lbm_dispatch.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_literal.hpp"
 #include "lbm_method.hpp"
+
+static_assert(lbm::kSpaceSrt == lbm::SRT, "SRT space id");
+static_assert(lbm::kLitA == lbm::LIT_A && lbm::kLitB == lbm::LIT_B && lbm::kLitC == lbm::LIT_C, "literal form ids");
 
 namespace lbm {
 
@@ -41,6 +45,7 @@ namespace lbm {
 const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweep, sp, eq, reg, pat) }
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
 const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
+const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -120,12 +125,18 @@ struct lbm_ctx {
   bool vec = false;   // vectorised sweep (V cells per lane) where the shape allows it
   int lds = 0;        // dynamic LDS reserved per sweep block: caps resident blocks per CU
   int transform = 0;  // LBM_TRANSFORM_CHIMERA or LBM_TRANSFORM_DENSE_MFMA (ablation)
+  bool literal = false;  // LBM_ARITH_LITERAL: the collision form evaluated as written
+  int form = 0;          // its form (kLitA / kLitB / kLitC)
   bool graphs = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
   size_t staging_doubles = 0;
   double *partials = nullptr;
   int diag_blocks = 0;
+  // block -> tile tables of the sweep for the current launch shape (index 1: vectorised);
+  // tile_key is the (bx, by, swz) they were built for
+  uint2 *tiles[2] = {nullptr, nullptr};
+  int tile_key[3] = {0, 0, -1};
 };
 
 namespace lbm {
@@ -133,6 +144,58 @@ namespace lbm {
 static int vec_width(int store) { return store == F16 ? 4 : 2; }
 // the vectorised kernel runs when every wave covers whole 64 V-cell chunks of one row
 static bool vec_ok(const lbm_ctx *c, int bx) { return bx % 64 == 0 && c->nx % (bx * vec_width(c->store)) == 0; }
+
+// Host copy of the device's XCD order: 8 XCDs take workgroups round-robin, so block b runs
+// on XCD b % 8; give each XCD a contiguous range of tiles (its own part of the box in L2).
+static uint32_t xcd_tile_host(uint32_t b, uint32_t n) {
+  const uint32_t per = n / 8u, rem = n % 8u;
+  const uint32_t xcd = b % 8u, local = b / 8u;
+  return xcd < rem ? xcd * (per + 1u) + local : rem * (per + 1u) + (xcd - rem) * per + local;
+}
+
+static void free_tiles(lbm_ctx *c) {
+  for (int v = 0; v < 2; ++v) {
+    if (c->tiles[v]) (void)hipFree(c->tiles[v]);
+    c->tiles[v] = nullptr;
+  }
+  c->tile_key[2] = -1;
+}
+
+static const uint64_t MAX_TILE_TABLE = uint64_t(1) << 24;  // blocks; larger grids divide on the device
+
+// Build the block -> (tx, ty, tz) tables for the current launch shape, so the sweep reads its
+// tile with one scalar load instead of two integer divisions per block.  Called outside graph
+// capture (it allocates); a grid without a table falls back to the division path.
+static lbm_status ensure_tiles(lbm_ctx *c) {
+  if (c->tile_key[0] == c->bx && c->tile_key[1] == c->by && c->tile_key[2] == c->swz) return LBM_OK;
+  free_tiles(c);
+  const char *env = std::getenv("LBM_TILE_TABLE");
+  const bool use_table = !(env && env[0] == '0');
+  for (int v = 0; v < 2 && use_table; ++v) {
+    if (v == 1 && !vec_ok(c, c->bx)) continue;
+    const int cells_x = c->bx * (v ? vec_width(c->store) : 1);
+    const uint64_t tx = (uint64_t(c->nx) + cells_x - 1) / cells_x, ty = (uint64_t(c->ny) + c->by - 1) / c->by;
+    const uint64_t n = tx * ty * uint64_t(c->nz);
+    if (tx >= 65536 || ty >= 65536 || n > MAX_TILE_TABLE) continue;
+    std::vector<uint2> h(n);
+    for (uint64_t b = 0; b < n; ++b) {
+      const uint64_t tile = c->swz ? xcd_tile_host(uint32_t(b), uint32_t(n)) : b;
+      const uint64_t z = tile / (tx * ty), r = tile - z * tx * ty, y = r / tx, x = r - y * tx;
+      h[b] = make_uint2(uint32_t(x | (y << 16)), uint32_t(z));
+    }
+    hipError_t e = hipMalloc(&c->tiles[v], n * sizeof(uint2));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->tiles[v] = nullptr;
+      continue;  // no table: the kernel divides
+    }
+    HIPCHECK(hipMemcpy(c->tiles[v], h.data(), n * sizeof(uint2), hipMemcpyHostToDevice), "tile table copy");
+  }
+  c->tile_key[0] = c->bx;
+  c->tile_key[1] = c->by;
+  c->tile_key[2] = c->swz;
+  return LBM_OK;
+}
 
 template <class ST, class CT>
 static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void *dst, bool vec) {
@@ -149,6 +212,10 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.tiles_y = (c->ny + c->by - 1) / c->by;
   a.swizzle = c->swz;
   a.absolute = c->p.zero_centered ? 0 : 1;
+  a.bx = c->bx;
+  a.by = c->by;
+  const bool table_ok = c->tile_key[0] == c->bx && c->tile_key[1] == c->by && c->tile_key[2] == c->swz;
+  a.tile_table = table_ok ? c->tiles[vec ? 1 : 0] : nullptr;
   a.grav = CT(c->p.gravity);
   for (int j = 0; j < 6; ++j)
     for (int k = 0; k < 6; ++k) a.R.b2[j][k] = CT(c->R.b2[j][k]);
@@ -217,7 +284,11 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     src = c->buf[0];
     dst = c->buf[0];
   }
-  if (c->transform == LBM_TRANSFORM_DENSE_MFMA && sp_override < 0) {
+  if (c->literal && sp_override < 0) {
+    const void *fn = sweep_literal_fn(c->s, c->store, sp, c->form);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no literal-arithmetic kernel for this method");
+    HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
+  } else if (c->transform == LBM_TRANSFORM_DENSE_MFMA && sp_override < 0) {
     const void *fn = sweep_mfma_fn(c->s, c->store, sp, reg);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no MFMA ablation kernel for this method");
     HIPCHECK(launch_sweep_lds(c, fn, src, dst, mfma_lds_bytes(c)), "sweep launch");
@@ -308,7 +379,9 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   c->s = p->stencil;
   c->q = stencil_q(p->stencil);
   c->d = stencil_d(p->stencil);
-  c->space = p->space;
+  c->space = internal_space(p->space);
+  c->literal = p->arithmetic == LBM_ARITH_LITERAL;
+  c->form = literal_form(p);
   c->eq = p->equilibrium == LBM_EQ_SHALLOW_WATER ? SWE : MAXWELL;
   c->store = p->storage;
   c->pattern = p->streaming;
@@ -386,6 +459,7 @@ extern "C" void lbm_destroy(lbm_ctx *c) {
     if (c->own[k] && c->buf[k]) (void)hipFree(c->buf[k]);
   if (c->staging) (void)hipFree(c->staging);
   if (c->partials) (void)hipFree(c->partials);
+  free_tiles(c);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -428,6 +502,8 @@ static lbm_status graph_for(lbm_ctx *c, int64_t n, hipGraphExec_t *out) {
   if (it == c->gcache.end()) {
     const int cur0 = c->cur;
     const int64_t t0 = c->t;
+    lbm_status st = ensure_tiles(c);
+    if (st != LBM_OK) return st;
     HIPCHECK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "begin capture");
     lbm_status s = LBM_OK;
     for (int64_t k = 0; k < n && s == LBM_OK; ++k) s = one_step(c);
@@ -456,6 +532,8 @@ extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   if (n < 0) return fail(LBM_EINVAL, "n must be >= 0");
   if (n == 0) return LBM_OK;
   if (!c->graphs || n < 2) {
+    lbm_status st = ensure_tiles(c);
+    if (st != LBM_OK) return st;
     for (int64_t k = 0; k < n; ++k) {
       lbm_status s = one_step(c);
       if (s != LBM_OK) return s;
@@ -480,6 +558,8 @@ extern "C" lbm_status lbm_graph_prepare(lbm_ctx *c, int64_t n) {
 
 extern "C" lbm_status lbm_debug_stream_only(lbm_ctx *c, int64_t n) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  lbm_status st = ensure_tiles(c);
+  if (st != LBM_OK) return st;
   for (int64_t k = 0; k < n; ++k) {
     lbm_status s = one_step(c, IDENTITY);
     if (s != LBM_OK) return s;
@@ -645,8 +725,10 @@ extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
   if (transform != LBM_TRANSFORM_CHIMERA && transform != LBM_TRANSFORM_DENSE_MFMA)
     return fail(LBM_EINVAL, "transform out of range");
   if (transform == LBM_TRANSFORM_DENSE_MFMA) {
-    if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL)
-      return fail(LBM_EUNSUPPORTED, "the MFMA ablation covers D3Q27, pull streaming, Maxwellian equilibrium");
+    if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL || c->space == SRT || c->literal)
+      return fail(LBM_EUNSUPPORTED,
+                  "the MFMA ablation covers D3Q27 moment spaces, pull streaming, Maxwellian equilibrium, "
+                  "deviation arithmetic");
     if (c->bx * c->by > 256 || (c->bx * c->by) % 64 != 0)
       return fail(LBM_EUNSUPPORTED, "the MFMA ablation needs blocks of 64..256 threads (whole waves)");
   }
@@ -713,7 +795,8 @@ extern "C" lbm_status lbm_time_steps(lbm_ctx *c, int64_t n, double *ms) {
 static std::string tune_key(const lbm_ctx *c) {
   std::ostringstream k;
   k << "s" << c->s << "_sp" << c->space << "_eq" << c->eq << "_r" << int(c->reg) << "_st" << c->store << "_pat"
-    << c->pattern << "_lay" << c->layout << "_" << c->nx << "x" << c->ny << "x" << c->nz;
+    << c->pattern << "_lay" << c->layout << (c->literal ? "_lit" + std::to_string(c->form) : std::string())
+    << (c->p.zero_centered ? "" : "_abs") << "_" << c->nx << "x" << c->ny << "x" << c->nz;
   return k.str();
 }
 
@@ -1032,12 +1115,14 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   if (common->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the pull pattern");
   if (common->equilibrium != LBM_EQ_MAXWELLIAN) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the Maxwellian");
   if (!common->zero_centered) return fail(LBM_EUNSUPPORTED, "the batched ensemble stores zero-centred populations");
+  if (common->arithmetic != LBM_ARITH_DEVIATION)
+    return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the deviation arithmetic");
   lbm_batch *b = new lbm_batch();
   b->p = *common;
   b->s = common->stencil;
   b->q = stencil_q(b->s);
   b->d = 3;
-  b->space = common->space;
+  b->space = internal_space(common->space);
   b->store = common->storage;
   b->elem = storage_bytes(b->store);
   b->nboxes = nboxes;

@@ -15,12 +15,13 @@ LIB_PATH = os.path.join(_HERE, "libpaper_lbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
 STENCILS = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
-SPACES = {"raw": 0, "central": 1, "cumulant": 2}
+SPACES = {"raw": 0, "central": 1, "cumulant": 2, "srt": 3}
 EQUILIBRIA = {"maxwellian": 0, "swe": 1}
 EQ_FORMS = {"default": 0, "absolute": 1, "delta": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 STREAMING = {"pull": 0, "aa": 1}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
+ARITHMETIC = {"deviation": 0, "literal": 1}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
@@ -31,7 +32,7 @@ class LbmParams(ctypes.Structure):
                 ("gravity", c_double), ("nx", c_int64), ("ny", c_int64), ("nz", c_int64),
                 ("periodic", c_int * 3), ("storage", c_int), ("streaming", c_int),
                 ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p),
-                ("layout", c_int)]
+                ("layout", c_int), ("arithmetic", c_int)]
 
 
 class LbmError(RuntimeError):
@@ -123,7 +124,7 @@ def _dptr(a):
 
 
 def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", equilibrium="maxwellian",
-                eq_form="default", gravity=0.0, zero_centered=1, layout="auto"):
+                eq_form="default", gravity=0.0, zero_centered=1, layout="auto", arithmetic="deviation"):
     p = LbmParams()
     check(load().lbm_params_default(ctypes.byref(p)))
     p.stencil = STENCILS[stencil]
@@ -140,6 +141,7 @@ def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", e
     p.storage = STORAGE[storage]
     p.streaming = STREAMING[streaming]
     p.layout = LAYOUTS[layout]
+    p.arithmetic = ARITHMETIC[arithmetic]
     return p
 
 
@@ -161,7 +163,7 @@ class Lattice:
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
                  equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto",
-                 zero_centered=True):
+                 zero_centered=True, arithmetic="deviation"):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
@@ -169,7 +171,7 @@ class Lattice:
         self.dims = tuple(int(v) for v in dims)
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
-                        zero_centered=1 if zero_centered else 0, layout=layout)
+                        zero_centered=1 if zero_centered else 0, layout=layout, arithmetic=arithmetic)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []

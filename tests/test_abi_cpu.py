@@ -81,6 +81,13 @@ def test_valid_parameter_sets():
     (dict(stencil="D2Q9", space="cumulant", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(dims=(65536, 4096, 2), storage="f32", layout="rows"), lbm.LBM_EUNSUPPORTED),
     (dict(layout="diagonal"), None),
+    (dict(space="srt", omegas=np.r_[np.zeros(4), np.full(22, 1.2), [1.3]]), lbm.LBM_EINVAL),
+    (dict(stencil="D2Q9", space="srt", omegas=np.r_[np.zeros(3), np.full(6, 1.2)], equilibrium="swe",
+          gravity=0.1), lbm.LBM_EUNSUPPORTED),
+    (dict(stencil="D3Q19", space="raw", arithmetic="literal"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="raw", arithmetic="literal", storage="f16"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="raw", arithmetic="literal", streaming="aa"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="cumulant", arithmetic="literal", eq_form="delta"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_invalid_parameter_sets(kw, code):
     if code is None:  # an unknown layout name never reaches the library
@@ -97,6 +104,45 @@ def test_layout_enum_checked_and_large_boxes_accepted():
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
     # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
     assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
+
+
+def test_srt_and_literal_parameter_sets():
+    for st in ("D2Q9", "D3Q19", "D3Q27"):
+        q = lbm.Q[st]
+        om = np.r_[np.zeros(3 if st == "D2Q9" else 4), np.full(q - (3 if st == "D2Q9" else 4), 1.3)]
+        assert lbm.lbm_validate(_p(stencil=st, space="srt", omegas=om)) == 0, lbm.last_error()
+    for st in ("D2Q9", "D3Q27"):
+        for sp in ("raw", "central", "cumulant", "srt"):
+            om = O.regularized_rates(st, 1.0) if sp == "srt" else O.regularized_rates(st, 1.7)
+            for zc, form in ((0, "default"), (1, "absolute"), (1, "delta"), (1, "default")):
+                if sp == "cumulant" and form == "delta":
+                    continue
+                for store in ("f64", "f32"):
+                    p = _p(stencil=st, space=sp, omegas=om, zero_centered=zc, eq_form=form, storage=store,
+                           arithmetic="literal")
+                    assert lbm.lbm_validate(p) == 0, (st, sp, zc, form, store, lbm.last_error())
+    p = _p()
+    p.arithmetic = 2
+    assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+
+
+def test_params_struct_layout_matches_the_header(tmp_path):
+    """The ctypes mirror of lbm_params has the C compiler's size and field offsets."""
+    fields = [f[0] for f in lbm.LbmParams._fields_]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "lbm.h"', "int main(void) {",
+             '  printf("sizeof %zu\\n", sizeof(lbm_params));']
+    lines += ['  printf("%s %%zu\\n", offsetof(lbm_params, %s));' % (f, f) for f in fields]
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                 check=True).stdout.splitlines())
+    import ctypes
+    assert int(out["sizeof"]) == ctypes.sizeof(lbm.LbmParams)
+    for f in fields:
+        assert int(out[f]) == getattr(lbm.LbmParams, f).offset, f
 
 
 def test_nonperiodic_rejected():

@@ -1,51 +1,80 @@
-"""Round-off plateau of the Taylor-Green energy decay (sec. 5.1, table of E/E0 after the
-vortex has decayed below the representable range): absolute against zero-centred storage.
+"""Round-off plateau of the Taylor-Green energy decay (sec. 5.1), at the paper's configuration:
+D3Q27, u0 = 0.25, nu = 1/6 (omega = 1), L = 256, 200 000 steps, FP64, for SRT, R-MRT, R-CM
+and R-K with every admissible combination of storage format and equilibrium form, each form
+evaluated literally (paper_2211_02435_amd.plateau).
 
-The z-invariant vortex of eq. TGA_init with u0 = 0.25 and nu = 1/6 (omega = 1, so every
-"R-" method relaxes all non-conserved quantities to equilibrium) decays as
-E/E0 = exp(-4 nu k^2 t).  On a 64 x 64 x 4 box (k = 2 pi / 64) the analytic ratio falls
-below 1e-40 within 20 000 steps, after which the simulated ratio stalls on a plateau set by
-round-off.  The paper's ordering is that zero-centred storage stalls orders of magnitude
-lower than absolute storage; this test measures both in FP64 on D3Q27 for raw moments,
-central moments and cumulants and checks that ordering.
+Checked against the paper's findings (text and table of sec. 5.1), not against fixed values:
+the analytic ratio exp(-4 nu k^2 t) = 1.8e-35 lies below every plateau; absolute storage stalls
+highest for every method; zero-centred storage with the delta-equilibrium stalls lowest where
+it is admissible; the cumulant method loses the most to absolute storage.  The vortex is
+z-invariant, so a 256 x 256 x 1 box stands for the 256^3 box (checked by comparing nz = 1
+and nz = 2 on a shorter run).
 """
 import math
 
 import numpy as np
 import pytest
 
-import lbm_workloads as W
-import oracle as O
 from paper_2211_02435_amd import lbm
+from paper_2211_02435_amd import plateau as PL
 
 pytestmark = pytest.mark.gpu
 
-N, NZ, STEPS = 64, 4, 20000
+N, STEPS = 256, 200000
+EPS = 2.0 ** -52
 
 
-def _plateau(space, zero_centered):
-    om = O.regularized_rates("D3Q27", 1.0)
-    rho, u = W.tgv2d_fields(N, N, NZ, u0=0.25)
-    lat = lbm.Lattice("D3Q27", space, om, (N, N, NZ), storage="f64", zero_centered=zero_centered)
-    lat.lbm_init_equilibrium(rho, u)
-    e0 = lat.lbm_diagnostics()[4]
-    lat.lbm_step(STEPS)
-    e = lat.lbm_diagnostics()[4]
-    return e / e0
+def _col(name):
+    return dict(PL.COLUMNS)[name]
 
 
-def test_zero_centred_storage_lowers_the_round_off_plateau():
+ABS, ZC_F, ZC_D, ZC_DEV = (c[0] for c in PL.COLUMNS)
+_cache = {}
+
+
+def _ratio(space, cname):
+    key = (space, cname)
+    if key not in _cache:
+        _cache[key] = PL.run(space, _col(cname), n=N, nz=1, steps=STEPS, every=STEPS)["ratio"]
+        print("%-9s %-36s E/E0 = %.2e" % (space, cname, _cache[key]), flush=True)
+    return _cache[key]
+
+
+def test_z_invariant_box_stands_for_the_cube():
+    om = np.ones(27)
+    col = _col(ZC_F)
+    lat1 = lbm.Lattice("D3Q27", "cumulant", om, (64, 64, 1), storage="f64", **col)
+    lat2 = lbm.Lattice("D3Q27", "cumulant", om, (64, 64, 2), storage="f64", **col)
+    import lbm_workloads as W
+    for lat, nz in ((lat1, 1), (lat2, 2)):
+        rho, u = W.tgv2d_fields(64, 64, nz, u0=0.25)
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_step(500)
+    p1, p2 = lat1.lbm_get_populations(), lat2.lbm_get_populations()
+    assert np.array_equal(p2[:, 0], p2[:, 1])
+    assert np.array_equal(p1[:, 0], p2[:, 0])
+
+
+@pytest.mark.parametrize("space", ["srt", "raw", "central", "cumulant"])
+def test_plateau_ordering_of_the_storage_and_equilibrium_forms(space):
     nu = 1.0 / 6.0
-    k = 2 * math.pi / N
-    analytic = math.exp(-4 * nu * k * k * STEPS)
-    rows = []
-    for space in ("raw", "central", "cumulant"):
-        a = _plateau(space, False)
-        z = _plateau(space, True)
-        rows.append((space, a, z))
-        print("E/E0 after %d steps (analytic %.2e): %-8s absolute %.2e  zero-centred %.2e"
-              % (STEPS, analytic, space, a, z))
-    for space, a, z in rows:
-        assert a > 100 * analytic, "the absolute-storage run must have stalled on its plateau"
-        assert z < a / 100, (space, a, z)
-        assert z < 1e-28, (space, z)
+    k = 2.0 * math.pi / N
+    analytic = math.exp(-4.0 * nu * k * k * STEPS)
+    a = _ratio(space, ABS)
+    c = _ratio(space, ZC_F)
+    d = _ratio(space, ZC_D) if space != "cumulant" else None
+    v = _ratio(space, ZC_DEV)
+    print("%s: analytic %.2e absolute %.2e zc f_eq %.2e zc delta %s deviation %.2e"
+          % (space, analytic, a, c, "-" if d is None else "%.2e" % d, v))
+    # every run has stalled on a plateau above the analytic value
+    for r in (a, c, v) + ((d,) if d is not None else ()):
+        assert r > 10 * analytic
+    # absolute storage stalls highest; zero-centred storage lowers the plateau
+    assert c < a and v < a
+    if d is not None:
+        assert d < a
+    if space in ("raw", "central"):
+        assert d <= c  # the delta-equilibrium does at least as well as the absolute one
+    # zero-centred storage reaches the level of eps^2 (E is quadratic in u)
+    best = min(x for x in (c, d, v) if x is not None)
+    assert best < 100 * EPS * EPS

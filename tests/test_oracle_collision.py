@@ -113,6 +113,83 @@ def test_raw_equal_rates_is_bgk(name):
     np.testing.assert_allclose(out, want, rtol=0, atol=4e-15)
 
 
+def _srt(name, omega):
+    st = O.stencil(name)
+    om = np.full(st.q, omega)
+    om[st.conserved] = 0
+    return O.Method(name, "srt", om)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_srt_equilibrium_moments(name):
+    """The polynomial equilibrium carries the Maxwellian's moments up to second order:
+    sum f = rho, sum f xi = rho u, sum f xi_a xi_b = rho (cs2 delta_ab + u_a u_b)."""
+    st = O.stencil(name)
+    rng = np.random.default_rng(7)
+    rho = 1 + 0.1 * rng.standard_normal(5)
+    u = rng.uniform(-0.1, 0.1, (5, 3))
+    if st.d == 2:
+        u[:, 2] = 0
+    feq = O.srt_equilibrium(st, rho, u)
+    for n in range(5):
+        m0 = sum(feq[n, i] for i in range(st.q))
+        assert abs(m0 - rho[n]) < 1e-15
+        for a in range(st.d):
+            m1 = sum(feq[n, i] * st.xi[i, a] for i in range(st.q))
+            assert abs(m1 - rho[n] * u[n, a]) < 1e-15
+            for b in range(st.d):
+                m2 = sum(feq[n, i] * st.xi[i, a] * st.xi[i, b] for i in range(st.q))
+                want = rho[n] * ((1 / 3 if a == b else 0.0) + u[n, a] * u[n, b])
+                assert abs(m2 - want) < 1e-15
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_srt_forms_agree_conserve_and_relax(name):
+    m = _srt(name, 1.43)
+    df = _state(m)
+    a = O.collide_cells(m, df + m.f0, "absolute") - m.f0
+    b = O.collide_cells(m, df, "delta")
+    c = O.collide_cells(m, df, "zc_absolute")
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(c, b, rtol=0, atol=1e-15)
+    xi = m.st.xi.astype(float)
+    np.testing.assert_allclose(b.sum(axis=1), df.sum(axis=1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(b @ xi, df @ xi, rtol=0, atol=1e-15)
+    # unit rate: the post-collision state is the equilibrium of the pre-collision moments
+    m1 = _srt(name, 1.0)
+    rho, u = O.macroscopic_from_delta(m1, df)
+    np.testing.assert_allclose(O.collide_cells(m1, df, "delta"),
+                               O.srt_equilibrium(m1.st, rho, u) - m1.f0, rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q27"])
+def test_srt_equals_raw_moment_bgk_on_tensor_product_stencils(name):
+    """On D2Q9 and D3Q27 (products of the 1-D three-velocity set) the polynomial equilibrium is
+    M^-1 of the raw Maxwellian moments truncated at second order, so one SRT collision equals
+    the raw-moment collision with every rate omega."""
+    st = O.stencil(name)
+    m = _srt(name, 1.21)
+    om = np.full(st.q, 1.21)
+    om[st.conserved] = 0
+    raw = O.Method(name, "raw", om)
+    df = _state(m)
+    np.testing.assert_allclose(O.collide_cells(m, df, "delta"), O.collide_cells(raw, df, "delta"),
+                               rtol=0, atol=2e-15)
+
+
+def test_srt_differs_from_raw_moment_bgk_on_d3q19():
+    """D3Q19 lacks the corner velocities: its polynomial equilibrium has m_xxyy =
+    rho (1/9 + (ux^2 + uy^2) / 3 - uz^2 / 6), not the truncated Maxwellian's
+    rho (1/9 + (ux^2 + uy^2) / 3)."""
+    st = O.stencil("D3Q19")
+    rho = np.array([1.0])
+    u = np.array([[0.03, -0.02, 0.05]])
+    feq = O.srt_equilibrium(st, rho, u)[0]
+    m220 = sum(feq[i] * st.xi[i, 0] ** 2 * st.xi[i, 1] ** 2 for i in range(st.q))
+    want = 1 / 9 + (0.03 ** 2 + 0.02 ** 2) / 3 - 0.05 ** 2 / 6
+    assert abs(m220 - want) < 1e-16
+
+
 def test_worked_propagation_example():
     """sec. 4.3: without a force the post-collision first-order raw moment is rho u_x."""
     m = O.Method("D3Q27", "central", _general_rates("D3Q27", 5))
