@@ -82,7 +82,14 @@ typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_stencil;
  * equilibrium is the second-order polynomial f_eq_i = w_i rho (1 + 3 xi.u + 9/2 (xi.u)^2
  * - 3/2 u.u), and every rate of a non-conserved polynomial must be the same omega. */
 typedef enum { LBM_SPACE_RAW = 0, LBM_SPACE_CENTRAL = 1, LBM_SPACE_CUMULANT = 2, LBM_SPACE_SRT = 3 } lbm_space;
-typedef enum { LBM_EQ_MAXWELLIAN = 0, LBM_EQ_SHALLOW_WATER = 1 } lbm_equilibrium;
+/* LBM_EQ_SHALLOW_WATER_CONTINUOUS: Venturi's shallow-water equilibrium, the continuous
+ * Maxwellian of sec. 2.4 with density h and squared speed of sound c^2 = g h / 2 (sec. 5.2),
+ * used exactly in central-moment or cumulant space; background f0 = f^eq(h = 1, u = 0). */
+typedef enum {
+  LBM_EQ_MAXWELLIAN = 0,
+  LBM_EQ_SHALLOW_WATER = 1,
+  LBM_EQ_SHALLOW_WATER_CONTINUOUS = 2
+} lbm_equilibrium;
 /* DEFAULT resolves to DELTA for raw and central moments and SRT with the Maxwellian, to
  * ABSOLUTE for cumulants and for the shallow-water equilibrium. */
 typedef enum { LBM_EQFORM_DEFAULT = 0, LBM_EQFORM_ABSOLUTE = 1, LBM_EQFORM_DELTA = 2 } lbm_eq_form;
@@ -120,7 +127,7 @@ typedef struct {
   int zero_centered;      /* 1: store df = f - f0 (sec. 2.1); 0: store absolute f (Maxwellian) */
   const double *omegas;   /* host array of n_omegas rates, basis order above, each in [0, 2]  */
   int n_omegas;           /* == q                                                             */
-  double gravity;         /* g > 0 for LBM_EQ_SHALLOW_WATER, ignored otherwise                */
+  double gravity;         /* g > 0 for the shallow-water equilibria, ignored otherwise        */
   int64_t nx, ny, nz;     /* lattice size; nz == 1 for D2Q9                                   */
   int periodic[3];        /* must be {1, 1, 1}                                                */
   int storage;            /* lbm_storage                                                      */
@@ -130,6 +137,8 @@ typedef struct {
   void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
   int layout;             /* lbm_layout of the device population buffers                      */
   int arithmetic;         /* lbm_arithmetic of the collision                                  */
+  double force[3];        /* constant body force per cell and step (lattice units), Guo's     */
+                          /* model; {0, 0, 0} for none.  See lbm_set_force_field.             */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -144,7 +153,8 @@ lbm_status lbm_params_default(lbm_params *p);
  * rates, gravity <= 0 with the shallow-water equilibrium.  LBM_EUNSUPPORTED for the
  * restrictions of sec. 3 (delta-equilibrium needs zero-centred storage; the cumulant space
  * admits no delta-equilibrium), absolute storage with the shallow-water equilibrium, D2Q9 with
- * nz != 1, the shallow-water equilibrium on a 3-D stencil or in cumulant space, non-periodic
+ * nz != 1, the shallow-water equilibria on a 3-D stencil, Zhou's in cumulant space, Venturi's
+ * outside central and cumulant space, non-periodic
  * axes, SRT with unequal rates (EINVAL) or the shallow-water equilibrium, LITERAL arithmetic
  * outside D2Q9/D3Q27, F64/F32, pull, Maxwellian.
  * Absolute storage keeps f = df + w in the buffers (the "absolute" storage format of the
@@ -180,6 +190,17 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
  * recording cost stays out of a timed region.  No effect for n < 2 or with graphs off. */
 lbm_status lbm_graph_prepare(lbm_ctx *ctx, int64_t n);
 
+/* Body force field (sec. 2.1 source term, eq. MrtUpdateGeneral's q^F) with Guo's model:
+ * F[d * ncells + cell], d = 0..2, FP64, host or device pointer, copied (in the compute
+ * precision) and added to the constant params.force in every following step; NULL removes
+ * it.  With a force the equilibrium velocity is u = (j + F/2) / rho, the source's moments in
+ * the collision space (raw moments, or central moments for the central and cumulant spaces;
+ * the populations themselves for SRT) are added weighted by (I - S/2), every cell gains F of
+ * momentum per step, and lbm_macroscopic reports that u.  Forced steps use the general
+ * (non-regularized) kernels; not with LITERAL arithmetic, the shallow-water equilibria, the
+ * MFMA ablation or the batched ensemble (LBM_EUNSUPPORTED).  Synchronous. */
+lbm_status lbm_set_force_field(lbm_ctx *ctx, const double *F);
+
 /* Density (or h) and velocity of df(t), FP64, synchronous. */
 lbm_status lbm_macroscopic(lbm_ctx *ctx, double *rho, double *u);
 
@@ -189,7 +210,7 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, double *df);
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *df);
 
 /* FP64 reductions over df(t): out = {sum drho, sum jx, sum jy, sum jz,
- * sum rho |u|^2 / 2, number of non-finite populations}.  Deterministic (fixed-order tree).
+ * sum rho |u|^2 / 2 with u = j / rho, number of non-finite populations}.  Deterministic (fixed-order tree).
  * Returns LBM_ENONFINITE when out[5] > 0 (out is still filled).  Synchronous. */
 lbm_status lbm_diagnostics(lbm_ctx *ctx, double out[6]);
 

@@ -104,6 +104,31 @@ def swe_bumps(n, seed=0, nbumps=16, amp=0.1, sigma=(20.0, 100.0)):
     return h[None], np.zeros((3, 1, n, n))
 
 
+DAM_BREAK = dict(domain_m=40.0, cells=100, dt_s=0.05, nu_m2_per_s=1.0, g_m_per_s2=9.81,
+                 radius_m=2.5, column_m=2.5, depth_m=0.5)
+
+
+def dam_break_lattice(p=DAM_BREAK):
+    """Lattice parameters of the circular dam break of sec. 5.2: dx = domain / cells; heights
+    stay in metres, so the lattice gravity is g dt^2 / dx^2 (g h then has lattice units of
+    velocity squared); nu_lattice = nu dt / dx^2."""
+    dx = p["domain_m"] / p["cells"]
+    return {"dx": dx, "gravity": p["g_m_per_s2"] * p["dt_s"] ** 2 / dx ** 2,
+            "nu": p["nu_m2_per_s"] * p["dt_s"] / dx ** 2}
+
+
+def dam_break_fields(p=DAM_BREAK):
+    """Water column of the given radius and height at the centre of the periodic square domain,
+    the rest at the base depth, fluid at rest (sec. 5.2).  Node (i, j) sits at (i dx, j dx), the
+    column centre at (domain / 2, domain / 2).  Returns h (1, n, n) and u (3, 1, n, n)."""
+    n = p["cells"]
+    dx = p["domain_m"] / n
+    x = np.arange(n) * dx - 0.5 * p["domain_m"]
+    r2 = x[None, :] ** 2 + x[:, None] ** 2
+    h = np.where(r2 < p["radius_m"] ** 2, p["column_m"], p["depth_m"])
+    return h[None].astype(np.float64), np.zeros((3, 1, n, n))
+
+
 def batch_ensemble(nboxes=256, seed=0, edges=(32, 48, 64, 96), nu_range=(1e-4, 1e-1),
                    u0_range=(0.01, 0.05)):
     """Parameters of an ensemble of independent periodic cubes: edge uniform in `edges`,

@@ -23,6 +23,11 @@ tests/test_oracle_*.py check it against something other than itself):
   equilibrium_mono           sec. 2.4 (continuous Maxwellian, raw moments truncated at
                              second order in u as stated in sec. 4.3), sec. 5.2 (Zhou)
         pin: textbook D2Q9/D3Q27 polynomial equilibrium, SWE moments h, hu, gh^2/2 + huu
+  swe_maxwellian_mono        sec. 5.2, Venturi's cumulant shallow-water method: the continuous
+                             Maxwellian with c_s^2 = g h / 2
+        pin: population moments h, hu, g h^2 / 2 + h u u (the shallow-water flux, the same as
+             Zhou's discrete equilibrium); product form over the axes; the central-moment and
+             cumulant spaces give the same equilibrium populations
   collide                    eq. MrtUpdateGeneral, eq. MrtUpdateGeneralDeviationOnly,
                              eq. MrtUpdateAbsoluteFromZeroCentered (sec. 2.2)
         pin: the three forms agree, equilibrium is a fixed point, per-cell conservation,
@@ -34,6 +39,13 @@ tests/test_oracle_*.py check it against something other than itself):
         pin: moments of orders 0..2 are rho, rho u, rho (cs2 delta + u u) on every stencil;
              on the tensor-product stencils D2Q9 / D3Q27 one SRT collision equals the
              raw-moment collision with all rates omega (moment-space BGK)
+  guo_source / force         source term f^F of eq. LbUpdateScheme and q^F of
+                             eq. MrtUpdateGeneral (sec. 2.1, 2.2) with Guo's force model: the
+                             equilibrium velocity u = (j + F/2) / rho, q^F the source's moments
+                             in the collision space at u, weighted by (I - S/2)
+        pin: every cell gains exactly F of momentum and no mass; a uniform force accelerates a
+             uniform state by F / rho per step; the steady Kolmogorov flow under
+             F_x = F0 sin(k y) has the analytic amplitude F0 / (nu k^2) to second order
   stream                     eq. LbUpdateScheme (sec. 2.1), periodic
         pin: impulse moves by xi_i; N steps of pure streaming on an N-periodic box return
              the initial state
@@ -231,7 +243,8 @@ def partition_terms(e):
 
 def cumulants_from_central(st, kappa, rho, u):
     """Rescaled monomial cumulants C (n, q) from monomial central moments kappa (n, q).
-    Orders 0 and 1 hold the conserved (rho, rho*u)."""
+    Orders 0 and 1 hold the conserved (rho, rho*u); orders >= 2 are taken in the co-moving
+    frame, where the first-order central moments vanish (their blocks are dropped)."""
     k = kappa / rho[:, None]
     out = np.empty_like(kappa)
     for j, e in enumerate(st.exps):
@@ -243,6 +256,8 @@ def cumulants_from_central(st, kappa, rho, u):
         else:
             c = np.zeros_like(rho)
             for (nb, blocks), mult in partition_terms(e).items():
+                if any(sum(b) == 1 for b in blocks):
+                    continue  # a first-order factor: zero in the co-moving frame
                 term = np.full_like(rho, mult * math.factorial(nb - 1) * (-1.0) ** (nb - 1))
                 for b in blocks:
                     term = term * k[:, st.eidx[b]]
@@ -330,6 +345,30 @@ def srt_equilibrium(st, rho, u):
     return st.w[None, :] * rho[:, None] * (1.0 + xu / CS2 + xu * xu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2))
 
 
+def swe_maxwellian_mono(st, space, h, u, g):
+    """Equilibrium of Venturi's shallow-water method (sec. 5.2): the continuous Maxwellian of
+    sec. 2.4 with density h and squared speed of sound c^2 = g h / 2, as monomial central
+    moments h prod_d nu(E_d), nu = (1, 0, c^2), or as rescaled cumulants (C_000 = h,
+    C_100 = h u_x, C_010 = h u_y, C_200 = C_020 = h c^2, every other one zero)."""
+    c2 = 0.5 * g * h
+    out = np.zeros((h.shape[0], st.q))
+    for j, e in enumerate(st.exps):
+        n = sum(e)
+        if space == "central":
+            v = h.copy()
+            for d in range(3):
+                v = v * (1.0 if e[d] == 0 else (0.0 if e[d] == 1 else c2))
+            out[:, j] = v
+        else:
+            if n == 0:
+                out[:, j] = h
+            elif n == 1:
+                out[:, j] = h * u[:, e.index(1)]
+            elif n == 2 and max(e) == 2:
+                out[:, j] = h * c2
+    return out
+
+
 def swe_equilibrium(st, h, u, g):
     """Discrete shallow-water equilibrium of Zhou on D2Q9 (sec. 5.2, eq.
     DiscreteShallowWaterEquilibrium and the listing).  Reading: the last term of f_i,
@@ -353,7 +392,9 @@ def swe_equilibrium(st, h, u, g):
 class Method:
     """stencil, collision space, one relaxation rate per basis polynomial, equilibrium.
 
-    space: 'raw' | 'central' | 'cumulant' | 'srt'; equilibrium: 'maxwellian' | 'swe'.
+    space: 'raw' | 'central' | 'cumulant' | 'srt';
+    equilibrium: 'maxwellian' | 'swe' (Zhou's discrete equilibrium) | 'swe_maxwellian'
+    (Venturi's continuous Maxwellian with c^2 = g h / 2; central or cumulant space).
     Rates of the conserved polynomials (1, x, y, z) are ignored (pass-through).  'srt' works
     on the populations themselves with one rate, the common value of the non-conserved rates."""
 
@@ -372,6 +413,10 @@ class Method:
             assert stencil_name == "D2Q9" and space in ("raw", "central")
             # background: the rest state h = 1, u = 0 of the discrete equilibrium
             self.f0 = swe_equilibrium(self.st, np.ones(1), np.zeros((1, 3)), gravity)[0]
+        elif equilibrium == "swe_maxwellian":
+            assert stencil_name == "D2Q9" and space in ("central", "cumulant")
+            one, zero = np.ones(1), np.zeros((1, 3))
+            self.f0 = self.backward(swe_maxwellian_mono(self.st, space, one, zero, gravity), one, zero)[0]
         else:
             self.f0 = self.st.w.copy()
 
@@ -402,6 +447,8 @@ class Method:
         if self.equilibrium == "swe":
             feq = swe_equilibrium(st, rho, u, self.gravity)
             return self.forward(feq, rho, u)
+        if self.equilibrium == "swe_maxwellian":
+            return swe_maxwellian_mono(st, self.space, rho, u, self.gravity)
         if self.space == "srt":
             return srt_equilibrium(st, rho, u)
         if self.space == "raw":
@@ -409,6 +456,26 @@ class Method:
         if self.space == "central":
             return central_maxwellian(st, rho)
         return cumulant_maxwellian(st, rho, u)
+
+    def force_moments(self, S, u):
+        """q^F: the source populations S in the collision space at velocity u (monomial form);
+        for cumulants the source enters in central-moment space."""
+        st = self.st
+        if self.space == "srt":
+            return S
+        if self.space == "raw":
+            return S @ st.M.T
+        return np.einsum("nji,ni->nj", central_matrix(st, u), S)
+
+    def weighted_force(self, qF):
+        """(I - S/2) q^F in the polynomial basis; the conserved rows (rate 0) take all of q^F."""
+        st = self.st
+        if self.space == "srt":
+            return (1.0 - 0.5 * self.omegas[st.d + 1]) * qF
+        om = self.omegas.copy()
+        om[st.conserved] = 0.0
+        q = qF @ st.P.T
+        return np.linalg.solve(st.P, ((1.0 - 0.5 * om)[None, :] * q).T).T
 
     def relax(self, q_mono, q_eq_mono):
         """q = P q_mono; q* = q + S (q_eq - q) on non-conserved rows; back to monomials.
@@ -425,6 +492,16 @@ class Method:
         return np.linalg.solve(st.P, qs.T).T
 
 
+def guo_source(st, u, F):
+    """Guo's forcing populations (n, q): S_i = w_i [(xi_i - u) / cs2 + (xi_i . u) xi_i / cs2^2] . F
+    (the momentum source of sec. 2.1 in the model of Guo, Zheng and Shi)."""
+    xi = st.xi.astype(np.float64)
+    xu = u @ xi.T
+    xF = F @ xi.T
+    uF = (u * F).sum(axis=1)[:, None]
+    return st.w[None, :] * ((xF - uF) / CS2 + xu * xF / (CS2 * CS2))
+
+
 def macroscopic_from_delta(method, df_cells):
     """eq. DensityAndVelocityFromDeviation: rho = rho0 + sum df, u = sum df xi / rho."""
     st = method.st
@@ -433,15 +510,56 @@ def macroscopic_from_delta(method, df_cells):
     return rho, u
 
 
-def collide_cells(method, f_cells, form):
-    """Collision of every cell; f_cells is (n, q).
+def _collide_forced(m, f_cells, form, F):
+    """The three forms with Guo's source term: u = (j + F/2) / rho, q* = q + S(q_eq - q) +
+    (I - S/2) q^F.  For cumulants the relaxed cumulants return to central moments, whose
+    first-order entries keep their pre-collision value -F/2 (conserved), and (I - S/2) kappa^F
+    is added there."""
+    st = m.st
+    xi = st.xi.astype(np.float64)
+    f0 = m.f0[None, :]
+    if form == "absolute":
+        f_abs = f_cells
+        rho = f_cells.sum(axis=1)
+        j = f_cells @ xi
+    else:
+        f_abs = f_cells + f0
+        rho = 1.0 + f_cells.sum(axis=1)
+        j = f_cells @ xi
+    u = (j + 0.5 * F) / rho[:, None]
+    qFw = m.weighted_force(m.force_moments(guo_source(st, u, F), u))
+    if m.space == "cumulant":
+        if form == "delta":
+            raise ValueError("the cumulant transform is nonlinear: no delta-equilibrium (sec. 3)")
+        kappa = np.einsum("nji,ni->nj", central_matrix(st, u), f_abs)
+        C = cumulants_from_central(st, kappa, rho, u)
+        Cs = m.relax(C, m.equilibrium_mono(rho, u))
+        ks = central_from_cumulants(st, Cs, rho)
+        first = [k for k, e in enumerate(st.exps) if sum(e) == 1]
+        ks[:, first] = kappa[:, first]
+        ks = ks + qFw
+        out = np.linalg.solve(central_matrix(st, u), ks[:, :, None])[:, :, 0]
+        return out if form == "absolute" else out - f0
+    if form == "delta":
+        dq = m.forward(f_cells, rho, u)
+        dq_eq = m.equilibrium_mono(rho, u) - m.forward(np.broadcast_to(m.f0, f_cells.shape), rho, u)
+        return m.backward(m.relax(dq, dq_eq) + qFw, rho, u)
+    qs = m.relax(m.forward(f_abs, rho, u), m.equilibrium_mono(rho, u)) + qFw
+    out = m.backward(qs, rho, u)
+    return out if form == "absolute" else out - f0
+
+
+def collide_cells(method, f_cells, form, F=None):
+    """Collision of every cell; f_cells is (n, q); F (n, 3) an optional body force per cell
+    (Guo's model, see _collide_forced).
 
     form 'absolute'    : eq. MrtUpdateGeneral on absolute populations (input/output f).
     form 'delta'       : eq. MrtUpdateGeneralDeviationOnly (linear T only; input/output df).
-    form 'zc_absolute' : eq. MrtUpdateAbsoluteFromZeroCentered (input/output df).
-    No source term (q^F = 0)."""
+    form 'zc_absolute' : eq. MrtUpdateAbsoluteFromZeroCentered (input/output df)."""
     m = method
     st = m.st
+    if F is not None:
+        return _collide_forced(m, f_cells, form, np.asarray(F, dtype=np.float64))
     if form == "absolute":
         rho = f_cells.sum(axis=1)
         u = (f_cells @ st.xi.astype(np.float64)) / rho[:, None]
@@ -466,7 +584,7 @@ def default_form(method):
     """Form evaluated by default: delta-equilibrium for raw and central moments with the
     Maxwellian, absolute equilibrium on zero-centred storage for cumulants and for the
     shallow-water equilibrium."""
-    if method.space == "cumulant" or method.equilibrium == "swe":
+    if method.space == "cumulant" or method.equilibrium in ("swe", "swe_maxwellian"):
         return "zc_absolute"
     return "delta"
 
@@ -474,13 +592,20 @@ def default_form(method):
 # --------------------------------------------------------------------------------------
 # Fields: natural SoA layout df[i, z, y, x]  (q, nz, ny, nx)
 # --------------------------------------------------------------------------------------
-def collide(method, df, form=None, chunk=4096):
+def collide(method, df, form=None, chunk=4096, force=None):
+    """force: None, a constant (3,) body force, or a field (3, nz, ny, nx)."""
     form = form or default_form(method)
     q = method.st.q
     cells = df.reshape(q, -1).T
+    Fc = None
+    if force is not None:
+        force = np.asarray(force, dtype=np.float64)
+        Fc = (np.broadcast_to(force[:, None], (3, cells.shape[0])) if force.ndim == 1
+              else force.reshape(3, -1)).T
     out = np.empty_like(cells)
     for s in range(0, cells.shape[0], chunk):
-        out[s:s + chunk] = collide_cells(method, np.ascontiguousarray(cells[s:s + chunk]), form)
+        out[s:s + chunk] = collide_cells(method, np.ascontiguousarray(cells[s:s + chunk]), form,
+                                         None if Fc is None else np.ascontiguousarray(Fc[s:s + chunk]))
     return out.T.reshape(df.shape)
 
 
@@ -494,10 +619,10 @@ def stream(method, f):
     return out
 
 
-def step(method, df, n=1, form=None):
-    """n time steps: collide, then stream (eq. LbUpdateScheme)."""
+def step(method, df, n=1, form=None, force=None):
+    """n time steps: collide (with the optional body force), then stream (eq. LbUpdateScheme)."""
     for _ in range(n):
-        df = stream(method, collide(method, df, form))
+        df = stream(method, collide(method, df, form, force=force))
     return df
 
 
@@ -520,11 +645,16 @@ def init_equilibrium(method, rho, u, chunk=4096):
     return out.T.reshape((method.st.q,) + shape)
 
 
-def macroscopic(method, df):
-    """rho (nz, ny, nx) and u (3, nz, ny, nx) of the canonical state df."""
+def macroscopic(method, df, force=None):
+    """rho (nz, ny, nx) and u (3, nz, ny, nx) of the canonical state df; with a body force the
+    velocity is Guo's u = (j + F/2) / rho."""
     q = method.st.q
     cells = df.reshape(q, -1).T
     rho, u = macroscopic_from_delta(method, cells)
+    if force is not None:
+        force = np.asarray(force, dtype=np.float64)
+        Fc = (np.broadcast_to(force[:, None], (3, cells.shape[0])) if force.ndim == 1 else force.reshape(3, -1)).T
+        u = u + 0.5 * Fc / rho[:, None]
     return rho.reshape(df.shape[1:]), u.T.reshape((3,) + df.shape[1:])
 
 

@@ -36,7 +36,9 @@ enum StencilId { D2Q9 = 0, D3Q19 = 1, D3Q27 = 2 };
 // SRT: single relaxation time in population space (eq. MrtUpdateGeneral with T = identity
 // and S = omega I); IDENTITY: streaming only (no collision)
 enum SpaceId { RAW = 0, CENTRAL = 1, CUMULANT = 2, IDENTITY = 3, SRT = 4 };
-enum EqId { MAXWELL = 0, SWE = 1 };
+// MAXWELL: continuous Maxwellian (sec. 2.4); SWE: Zhou's discrete shallow-water equilibrium;
+// SWEK: Venturi's shallow-water equilibrium, the continuous Maxwellian with c^2 = g h / 2 (sec. 5.2)
+enum EqId { MAXWELL = 0, SWE = 1, SWEK = 2 };
 // PULL: gather from x - xi.  AA_EVEN: own slots, write to the opposite slot.
 // AA_ODD: read opposite slot at x - xi, write own slot at x + xi.
 enum PatternId { PULL = 0, AA_EVEN = 1, AA_ODD = 2 };
@@ -378,11 +380,13 @@ LBM_HD T cum_222(const T *in, T rinv) {
 }
 
 // in-place map of orders >= 4 (orders 2, 3 are unchanged); REG: inputs of order >= 3 are 0
+// c2 is the equilibrium's squared speed of sound (1/3 for the Maxwellian, g h / 2 for SWEK;
+// the 3-D maps use 1/3)
 template <int S, int SIGN, bool REG, class T>
-LBM_HD void cumulant_map(T *v, T rinv) {
+LBM_HD void cumulant_map(T *v, T rinv, T c2 = Cs<T>::cs2) {
   if constexpr (Lat<S>::D == 2) {
     constexpr int e22 = mono(2, 2, 0), e20 = mono(2, 0, 0), e02 = mono(0, 2, 0), e11 = mono(1, 1, 0);
-    T lin = Cs<T>::cs2 * (v[e20] + v[e02]);
+    T lin = c2 * (v[e20] + v[e02]);
     T quad = (v[e20] * v[e02] + T(2) * v[e11] * v[e11]) * rinv;
     v[e22] = SIGN < 0 ? v[e22] - lin - quad : v[e22] + lin + quad;
   } else {
@@ -433,17 +437,78 @@ LBM_HD void swe_feq_dev(T *g9, T dh, T h, T ux, T uy, T grav) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Venturi's shallow-water equilibrium (D2Q9) as raw-moment deviations about the rest state
+// h = 1, u = 0 (whose squared speed of sound is c0 = g / 2):
+//   m_eq(a, b) = h prod_d mu(E_d),  mu = (1, u_d, c^2 + u_d^2),  c^2 = g h / 2.
+// The u-free part of a moment with k exponent-2 axes is c0^k (h^(k+1) - 1), written with
+// dh = h - 1 as dh, dh (2 + dh), dh (3 + dh (3 + dh)); every other term carries u.
+// ---------------------------------------------------------------------------------------
+template <class T>
+LBM_HD void swek_meq_dev(T *m, T dh, T h, const T *u, T grav) {
+  const T c0 = T(0.5) * grav;
+  const T c2 = c0 * h;
+  const T ux = u[0], uy = u[1];
+  const T uxx = ux * ux, uyy = uy * uy;
+  const T k1 = c0 * (dh * (T(2) + dh));
+  m[mono(0, 0, 0)] = dh;
+  m[mono(1, 0, 0)] = h * ux;
+  m[mono(0, 1, 0)] = h * uy;
+  m[mono(2, 0, 0)] = k1 + h * uxx;
+  m[mono(0, 2, 0)] = k1 + h * uyy;
+  m[mono(1, 1, 0)] = h * ux * uy;
+  m[mono(2, 1, 0)] = h * (c2 + uxx) * uy;
+  m[mono(1, 2, 0)] = h * ux * (c2 + uyy);
+  m[mono(2, 2, 0)] = c0 * c0 * (dh * (T(3) + dh * (T(3) + dh))) + h * (c2 * (uxx + uyy) + uxx * uyy);
+}
+
+// ---------------------------------------------------------------------------------------
+// Guo's forcing populations (the source term of eq. LbUpdateScheme, sec. 2.1):
+//   S_i = w_i [ (xi_i - u) / cs2 + (xi_i . u) xi_i / cs4 ] . F,  in grid order
+// ---------------------------------------------------------------------------------------
+template <int S, class T>
+LBM_HD void guo_source(T *src, const T *u, const T *F) {
+  using L = Lat<S>;
+  sfor<L::G>([&](auto E) { src[E] = T(0); });
+  const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    T xF = T(0), xu = T(0);
+    sfor<3>([&](auto Dd) {
+      constexpr int d = decltype(Dd)::value;
+      if constexpr (L::c(i, d) > 0) {
+        xF += F[d];
+        xu += u[d];
+      } else if constexpr (L::c(i, d) < 0) {
+        xF -= F[d];
+        xu -= u[d];
+      }
+    });
+    src[L::gidx(i)] = T(L::w(i)) * (T(3) * (xF - uF) + T(9) * xu * xF);
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // the collision in moment space: m holds dm = M df (exponent-grid order) on entry and the
 // post-collision dm* on exit.  Missing monomials (D3Q19) leave as zero.
 // ---------------------------------------------------------------------------------------
-template <int S, int SP, int EQ, bool REG, class T>
-LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav) {
+// With FORCE, F is the body force of the cell (Guo's model): the equilibrium velocity is
+// u = (j + F/2) / rho, the first-order non-equilibrium moments are -F/2, and the source
+// moments weighted by (I - P^-1 S P / 2) = (I + B) / 2 are added in the collision space
+// (raw moments, or central moments for the central and cumulant spaces); momentum grows by F.
+template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
+LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullptr) {
+  static_assert(!(FORCE && REG), "the forced collision uses the general kernel");
   constexpr int D = Lat<S>::D;
   constexpr int G = Lat<S>::G;
   constexpr int EX = 1, EY = 3, EZ = 9;
   const T drho = m[0];
-  const T jx = m[EX], jy = m[EY];
-  const T jz = (D == 3) ? m[EZ] : T(0);
+  T jx = m[EX], jy = m[EY];
+  T jz = (D == 3) ? m[EZ] : T(0);
+  if constexpr (FORCE) {
+    jx += T(0.5) * F[0];
+    jy += T(0.5) * F[1];
+    if constexpr (D == 3) jz += T(0.5) * F[2];
+  }
   const T rho = T(1) + drho;
   const T rinv = T(1) / rho;
   T u[3] = {jx * rinv, jy * rinv, jz * rinv};
@@ -454,6 +519,9 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav) {
   if constexpr (EQ == SWE) {
     swe_feq_dev(meq, drho, rho, u[0], u[1], grav);
     chimera_forward<S>(meq);
+  } else if constexpr (EQ == SWEK) {
+    static_assert(S == D2Q9, "the shallow-water equilibria are two-dimensional");
+    swek_meq_dev(meq, drho, rho, u, grav);
   } else {
     sfor<G>([&](auto E) {
       constexpr int e = decltype(E)::value;
@@ -465,34 +533,57 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav) {
     if constexpr (D == 3) meq[EZ] = jz;
   }
 
-  // non-equilibrium raw moments (orders >= 2)
+  // non-equilibrium raw moments (orders >= 2; with a force also order 1, where it is -F/2)
   T v[G];
   sfor<G>([&](auto E) {
     constexpr int e = decltype(E)::value;
-    if constexpr (Lat<S>::ord(e) < 2) v[e] = T(0);
+    if constexpr (Lat<S>::ord(e) == 0) v[e] = T(0);
+    else if constexpr (Lat<S>::ord(e) == 1) v[e] = FORCE ? m[e] - meq[e] : T(0);
     else if constexpr (REG && Lat<S>::ord(e) > 2) v[e] = T(0);
     else v[e] = m[e] - meq[e];
   });
 
+  // the source's moments (raw, shifted to central for the central and cumulant spaces),
+  // weighted by (I + B) / 2 on orders >= 2 and taken whole on the conserved orders
+  auto add_force = [&](T *vv, bool central) {
+    if constexpr (FORCE) {
+      T fs[G];
+      guo_source<S>(fs, u, F);
+      chimera_forward<S>(fs);
+      if (central) binomial<S>(fs, -u[0], -u[1], -u[2]);
+      T wfs[G];
+      sfor<G>([&](auto E) { wfs[E] = fs[E]; });
+      relax<S, false>(wfs, R);
+      sfor<G>([&](auto E) {
+        constexpr int e = decltype(E)::value;
+        if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 2) vv[e] += T(0.5) * (fs[e] + wfs[e]);
+        else if constexpr (Lat<S>::ord(e) == 1) vv[e] += fs[e];
+      });
+    }
+  };
+
   if constexpr (SP == RAW) {
     relax<S, REG>(v, R);
+    add_force(v, false);
   } else {
     // to central moments; with zero orders 0, 1 the order-2 entries are unchanged
     if constexpr (!REG) binomial<S>(v, -u[0], -u[1], -u[2]);
     if constexpr (SP == CENTRAL) {
       relax<S, REG>(v, R);
     } else {
-      if constexpr (!REG) cumulant_map<S, -1, false>(v, rinv);
+      const T c2 = EQ == SWEK ? T(0.5) * grav * rho : Cs<T>::cs2;
+      if constexpr (!REG) cumulant_map<S, -1, false>(v, rinv, c2);
       relax<S, REG>(v, R);
-      cumulant_map<S, +1, REG>(v, rinv);
+      cumulant_map<S, +1, REG>(v, rinv, c2);
     }
+    add_force(v, true);
     binomial<S>(v, u[0], u[1], u[2]);
   }
-  // dm* = dm_eq + non-equilibrium part; conserved moments exactly
+  // dm* = dm_eq + non-equilibrium part; conserved moments exactly (plus F with a force)
   sfor<G>([&](auto E) {
     constexpr int e = decltype(E)::value;
     if constexpr (!Lat<S>::has_mono_e(e)) m[e] = T(0);
-    else if constexpr (Lat<S>::ord(e) >= 2) m[e] = meq[e] + v[e];
+    else if constexpr (Lat<S>::ord(e) >= 2 || (FORCE && Lat<S>::ord(e) == 1)) m[e] = meq[e] + v[e];
   });
 }
 
@@ -519,8 +610,8 @@ LBM_HD void srt_feq_dev(T *feq, T drho, T rho, const T *u) {
   });
 }
 
-template <int S, class T>
-LBM_HD void collide_srt(T *g, const Relax<T> &R) {
+template <int S, class T, bool FORCE = false>
+LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr) {
   using L = Lat<S>;
   T drho = T(0), j[3] = {T(0), T(0), T(0)};
   sfor<L::Q>([&](auto I) {
@@ -533,6 +624,9 @@ LBM_HD void collide_srt(T *g, const Relax<T> &R) {
       else if constexpr (L::c(i, d) < 0) j[d] -= v;
     });
   });
+  if constexpr (FORCE) {
+    sfor<3>([&](auto Dd) { j[decltype(Dd)::value] += T(0.5) * F[decltype(Dd)::value]; });
+  }
   const T rho = T(1) + drho;
   const T rinv = T(1) / rho;
   const T u[3] = {j[0] * rinv, j[1] * rinv, j[2] * rinv};
@@ -543,18 +637,27 @@ LBM_HD void collide_srt(T *g, const Relax<T> &R) {
     constexpr int gi = L::gidx(decltype(I)::value);
     g[gi] = fma(b, g[gi] - feq[gi], feq[gi]);
   });
+  if constexpr (FORCE) {
+    T src[Lat<S>::G];
+    guo_source<S>(src, u, F);
+    const T wf = T(0.5) * (T(1) + b);  // 1 - omega / 2
+    sfor<L::Q>([&](auto I) {
+      constexpr int gi = L::gidx(decltype(I)::value);
+      g[gi] = fma(wf, src[gi], g[gi]);
+    });
+  }
 }
 
 // ---------------------------------------------------------------------------------------
 // the collision: g holds df (grid order, missing velocities zero) and receives df*
 // ---------------------------------------------------------------------------------------
-template <int S, int SP, int EQ, bool REG, class T>
-LBM_HD void collide(T *g, const Relax<T> &R, T grav) {
+template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
+LBM_HD void collide(T *g, const Relax<T> &R, T grav, const T *F = nullptr) {
   if constexpr (SP == SRT) {
-    collide_srt<S>(g, R);
+    collide_srt<S, T, FORCE>(g, R, F);
   } else if constexpr (SP != IDENTITY) {
     chimera_forward<S>(g);
-    collide_moments<S, SP, EQ, REG, T>(g, R, grav);
+    collide_moments<S, SP, EQ, REG, T, FORCE>(g, R, grav, F);
     chimera_inverse<S>(g);
   }
 }
@@ -566,6 +669,9 @@ LBM_HD void equilibrium_dev(T *g, T drho, const T *u, T grav) {
   const T rho = T(1) + drho;
   if constexpr (EQ == SWE) {
     swe_feq_dev(g, drho, rho, u[0], u[1], grav);
+  } else if constexpr (EQ == SWEK) {
+    swek_meq_dev(g, drho, rho, u, grav);
+    chimera_inverse<S>(g);
   } else if constexpr (SP == SRT) {
     sfor<G>([&](auto E) { g[E] = T(0); });
     srt_feq_dev<S>(g, drho, rho, u);

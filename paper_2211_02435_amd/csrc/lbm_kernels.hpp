@@ -49,6 +49,8 @@ struct SweepArgs {
   int absolute;      // nonzero: buffers hold absolute populations f = df + w
   int bx, by;        // block shape (threads along x, rows along y)
   const uint2 *tile_table;  // per block: (tx | ty << 16, tz), XCD order applied; or null
+  const CT *ffield;  // forced sweep: body force per cell [3][ncells] (natural order), or null
+  CT fconst[3];      // forced sweep: constant body force added to ffield
   CT grav;
   Relax<CT> R;
 };
@@ -180,7 +182,7 @@ struct NbrNat {
 // ---------------------------------------------------------------------------------------
 // fused stream + collide
 // ---------------------------------------------------------------------------------------
-template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT>
+template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT, bool FORCE = false>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
   using L = Lat<S>;
   const CellPos p = tile_cell_args(a, 1);
@@ -202,7 +204,20 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
   });
 
   if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
-  collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+  if constexpr (FORCE) {
+    CT F[3] = {a.fconst[0], a.fconst[1], a.fconst[2]};
+    if (a.ffield) {
+      const uint64_t nc = uint64_t(a.nx) * uint64_t(a.ny) * uint64_t(a.nz);
+      const uint64_t cell = (uint64_t(p.z) * uint64_t(a.ny) + uint64_t(p.y)) * uint64_t(a.nx) + uint64_t(p.x);
+      F[0] += a.ffield[cell];
+      F[1] += a.ffield[nc + cell];
+      F[2] += a.ffield[2 * nc + cell];
+    }
+    if constexpr (L::D == 2) F[2] = CT(0);
+    collide<S, SP, EQ, REG, CT, true>(g, a.R, a.grav, F);
+  } else {
+    collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+  }
   if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
 
   sfor<L::Q>([&](auto I) {
@@ -330,6 +345,10 @@ struct FieldArgs {
   double *partials;       // diagnostics: 6 per block
   int i0, i1;             // population range of export / import (chunking)
   int absolute;           // nonzero: buffers hold absolute populations f = df + w
+  int forced;             // nonzero: velocities are Guo's (j + F/2) / rho
+  const void *ffield;     // body force per cell [3][ncells] (double if ffield_f64, else float) or null
+  int ffield_f64;
+  double fconst[3];       // constant body force
 };
 
 // storage address (uniform part, lane part) of the canonical df_i(x) for layout GM
@@ -443,6 +462,17 @@ __global__ void __launch_bounds__(256) macro_kernel(FieldArgs a) {
   });
   const double rho = 1.0 + drho;
   const uint32_t self = nat_cell(a, p);
+  if (a.forced) {
+    sfor<3>([&](auto Dd) {
+      constexpr int d = decltype(Dd)::value;
+      double F = a.fconst[d];
+      if (a.ffield) {
+        const size_t k = size_t(d) * a.ncells + self;
+        F += a.ffield_f64 ? static_cast<const double *>(a.ffield)[k] : double(static_cast<const float *>(a.ffield)[k]);
+      }
+      if (L::D == 3 || d < 2) j[d] += 0.5 * F;
+    });
+  }
   a.rho_out[self] = rho;
   a.u_out[self] = j[0] / rho;
   a.u_out[size_t(a.ncells) + self] = j[1] / rho;

@@ -10,7 +10,11 @@
 //          equilibrium deviation formed by subtraction, dq_eq = q_eq(rho, u) - T(f0)
 //          (raw and central moments and SRT only: the transform must be linear in f);
 //   LIT_C  zero-centred storage, eq. MrtUpdateAbsoluteFromZeroCentered:  q = T(df + f0),
-//          df* = T^-1(q*) - f0.
+//          df* = T^-1(q*) - f0.  The raw-moment stage of T is linear, so the background
+//          enters as its raw moments, m = M df + m0, and leaves as dm* = m* - m0 before the
+//          inverse (where a generated kernel folds the constants f0); the nonlinear stages
+//          (central moments, cumulants, relaxation against the absolute equilibrium) run on
+//          the absolute moments.  SRT has T = identity: f = df + f0 per population.
 // Relaxation is q* = q_eq + (I - P^-1 S P)(q - q_eq) on the orders >= 2 in every form (the
 // conserved rows are carried), the same blocks as the default sweep.
 // Cumulants are absolute here: C = rho c with c the derivatives of the logarithm of the
@@ -144,8 +148,13 @@ LBM_HD void collide_literal(T *g, const Relax<T> &R) {
     using L = Lat<S>;
     constexpr int D = L::D, G = L::G;
     constexpr int EX = 1, EY = 3, EZ = 9;
-    if constexpr (FORM == LIT_C) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += T(L::w(I)); });
-    chimera_forward<S>(g);  // m = M f, or dm = M df for LIT_B
+    chimera_forward<S>(g);  // m = M f (LIT_A), or dm = M df
+    if constexpr (FORM == LIT_C) {
+      sfor<G>([&](auto E) {
+        constexpr int e = decltype(E)::value;
+        if constexpr (L::has_mono_e(e) && background_moment<e, T>() != T(0)) g[e] = g[e] + background_moment<e, T>();
+      });
+    }
     const T rho = FORM == LIT_B ? T(1) + g[0] : g[0];
     const T rinv = T(1) / rho;
     T u[3] = {g[EX] * rinv, g[EY] * rinv, D == 3 ? g[EZ] * rinv : T(0)};
@@ -197,8 +206,13 @@ LBM_HD void collide_literal(T *g, const Relax<T> &R) {
 
     if constexpr (SP == CUMULANT) lit_cumulant_map<S, +1>(g, rinv);
     if constexpr (SP != RAW) binomial<S>(g, u[0], u[1], u[2]);
+    if constexpr (FORM == LIT_C) {
+      sfor<G>([&](auto E) {
+        constexpr int e = decltype(E)::value;
+        if constexpr (L::has_mono_e(e) && background_moment<e, T>() != T(0)) g[e] = g[e] - background_moment<e, T>();
+      });
+    }
     chimera_inverse<S>(g);
-    if constexpr (FORM == LIT_C) sfor<L::Q>([&](auto I) { g[L::gidx(I)] -= T(L::w(I)); });
   }
 }
 

@@ -70,7 +70,7 @@ int literal_form(const lbm_params *p) {
 
 int resolve_eq_form(const lbm_params *p) {
   if (p->eq_form != LBM_EQFORM_DEFAULT) return p->eq_form;
-  if (p->space == LBM_SPACE_CUMULANT || p->equilibrium == LBM_EQ_SHALLOW_WATER) return LBM_EQFORM_ABSOLUTE;
+  if (p->space == LBM_SPACE_CUMULANT || p->equilibrium != LBM_EQ_MAXWELLIAN) return LBM_EQFORM_ABSOLUTE;
   return LBM_EQFORM_DELTA;
 }
 
@@ -237,7 +237,7 @@ lbm_status validate(const lbm_params *p) {
   if (p->space < LBM_SPACE_RAW || p->space > LBM_SPACE_SRT) return fail(LBM_EINVAL, "space out of range");
   if (p->arithmetic < LBM_ARITH_DEVIATION || p->arithmetic > LBM_ARITH_LITERAL)
     return fail(LBM_EINVAL, "arithmetic out of range");
-  if (p->equilibrium < LBM_EQ_MAXWELLIAN || p->equilibrium > LBM_EQ_SHALLOW_WATER)
+  if (p->equilibrium < LBM_EQ_MAXWELLIAN || p->equilibrium > LBM_EQ_SHALLOW_WATER_CONTINUOUS)
     return fail(LBM_EINVAL, "equilibrium out of range");
   if (p->eq_form < LBM_EQFORM_DEFAULT || p->eq_form > LBM_EQFORM_DELTA) return fail(LBM_EINVAL, "eq_form out of range");
   if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return fail(LBM_EINVAL, "storage out of range");
@@ -252,7 +252,7 @@ lbm_status validate(const lbm_params *p) {
     if (i > stencil_d(p->stencil) && (w < 0.0 || w > 2.0))
       return fail(LBM_EINVAL, "relaxation rate " + std::to_string(i) + " outside [0, 2]");
   }
-  if (p->equilibrium == LBM_EQ_SHALLOW_WATER && !(p->gravity > 0.0 && std::isfinite(p->gravity)))
+  if (p->equilibrium != LBM_EQ_MAXWELLIAN && !(p->gravity > 0.0 && std::isfinite(p->gravity)))
     return fail(LBM_EINVAL, "shallow-water equilibrium needs gravity > 0");
   // admissibility (sec. 3)
   if (!p->zero_centered) {
@@ -271,6 +271,13 @@ lbm_status validate(const lbm_params *p) {
       if (p->omegas[i] != p->omegas[stencil_d(p->stencil) + 1])
         return fail(LBM_EINVAL, "SRT needs one rate: every non-conserved rate must be equal");
   }
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(p->force[d])) return fail(LBM_EINVAL, "force must be finite");
+  const bool forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
+  if (forced && p->equilibrium != LBM_EQ_MAXWELLIAN)
+    return fail(LBM_EUNSUPPORTED, "the body force is implemented with the Maxwellian equilibrium");
+  if (forced && p->arithmetic == LBM_ARITH_LITERAL)
+    return fail(LBM_EUNSUPPORTED, "the body force runs with the deviation arithmetic");
   if (p->arithmetic == LBM_ARITH_LITERAL) {
     if (p->stencil != LBM_D2Q9 && p->stencil != LBM_D3Q27)
       return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for D2Q9 and D3Q27");
@@ -278,6 +285,13 @@ lbm_status validate(const lbm_params *p) {
     if (p->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic runs with pull streaming");
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
       return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for the Maxwellian equilibrium");
+  }
+  if (p->equilibrium == LBM_EQ_SHALLOW_WATER_CONTINUOUS) {
+    if (p->stencil != LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the shallow-water equilibria are two-dimensional (D2Q9)");
+    if (p->space != LBM_SPACE_CENTRAL && p->space != LBM_SPACE_CUMULANT)
+      return fail(LBM_EUNSUPPORTED, "the continuous shallow-water equilibrium is used in central-moment or cumulant space");
+    if (p->eq_form == LBM_EQFORM_DELTA)
+      return fail(LBM_EUNSUPPORTED, "the shallow-water equilibrium is relaxed in absolute form");
   }
   if (p->equilibrium == LBM_EQ_SHALLOW_WATER) {
     if (p->stencil != LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the shallow-water equilibrium is two-dimensional (D2Q9)");

@@ -46,6 +46,7 @@ const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_T
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
 const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
 const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
+const void *sweep_force_fn(int s, int store, int sp, int pat) { LBM_TABLE_CALL(sweep_force, sp, pat) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -127,6 +128,7 @@ struct lbm_ctx {
   int transform = 0;  // LBM_TRANSFORM_CHIMERA or LBM_TRANSFORM_DENSE_MFMA (ablation)
   bool literal = false;  // LBM_ARITH_LITERAL: the collision form evaluated as written
   int form = 0;          // its form (kLitA / kLitB / kLitC)
+  void *ffield = nullptr;  // body force per cell [3][ncells] in the compute precision, or null
   bool graphs = true;
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
@@ -151,6 +153,10 @@ static uint32_t xcd_tile_host(uint32_t b, uint32_t n) {
   const uint32_t per = n / 8u, rem = n % 8u;
   const uint32_t xcd = b % 8u, local = b / 8u;
   return xcd < rem ? xcd * (per + 1u) + local : rem * (per + 1u) + (xcd - rem) * per + local;
+}
+
+static bool forced(const lbm_ctx *c) {
+  return c->ffield || c->p.force[0] != 0.0 || c->p.force[1] != 0.0 || c->p.force[2] != 0.0;
 }
 
 static void free_tiles(lbm_ctx *c) {
@@ -217,6 +223,8 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   const bool table_ok = c->tile_key[0] == c->bx && c->tile_key[1] == c->by && c->tile_key[2] == c->swz;
   a.tile_table = table_ok ? c->tiles[vec ? 1 : 0] : nullptr;
   a.grav = CT(c->p.gravity);
+  a.ffield = static_cast<const CT *>(c->ffield);
+  for (int d = 0; d < 3; ++d) a.fconst[d] = CT(c->p.force[d]);
   for (int j = 0; j < 6; ++j)
     for (int k = 0; k < 6; ++k) a.R.b2[j][k] = CT(c->R.b2[j][k]);
   for (int j = 0; j < 7; ++j)
@@ -284,7 +292,11 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     src = c->buf[0];
     dst = c->buf[0];
   }
-  if (c->literal && sp_override < 0) {
+  if (forced(c) && sp_override < 0) {
+    const void *fn = sweep_force_fn(c->s, c->store, sp, pat);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no forced kernel for this method");
+    HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
+  } else if (c->literal && sp_override < 0) {
     const void *fn = sweep_literal_fn(c->s, c->store, sp, c->form);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no literal-arithmetic kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
@@ -315,6 +327,10 @@ static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
   a.buf = buf;
   a.L = c->L;
   a.absolute = c->p.zero_centered ? 0 : 1;
+  a.forced = forced(c) ? 1 : 0;
+  a.ffield = c->ffield;
+  a.ffield_f64 = c->store == F64 ? 1 : 0;
+  for (int d = 0; d < 3; ++d) a.fconst[d] = c->p.force[d];
   a.ncells = c->ncells;
   a.nx = c->nx;
   a.ny = c->ny;
@@ -382,7 +398,8 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   c->space = internal_space(p->space);
   c->literal = p->arithmetic == LBM_ARITH_LITERAL;
   c->form = literal_form(p);
-  c->eq = p->equilibrium == LBM_EQ_SHALLOW_WATER ? SWE : MAXWELL;
+  c->eq = p->equilibrium == LBM_EQ_SHALLOW_WATER ? SWE
+          : (p->equilibrium == LBM_EQ_SHALLOW_WATER_CONTINUOUS ? SWEK : MAXWELL);
   c->store = p->storage;
   c->pattern = p->streaming;
   c->nx = int(p->nx);
@@ -459,6 +476,7 @@ extern "C" void lbm_destroy(lbm_ctx *c) {
     if (c->own[k] && c->buf[k]) (void)hipFree(c->buf[k]);
   if (c->staging) (void)hipFree(c->staging);
   if (c->partials) (void)hipFree(c->partials);
+  if (c->ffield) (void)hipFree(c->ffield);
   free_tiles(c);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -563,6 +581,43 @@ extern "C" lbm_status lbm_debug_stream_only(lbm_ctx *c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     lbm_status s = one_step(c, IDENTITY);
     if (s != LBM_OK) return s;
+  }
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_set_force_field(lbm_ctx *c, const double *F) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  HIPCHECK(hipStreamSynchronize(c->stream), "force sync");
+  clear_graphs(c);
+  if (!F) {
+    if (c->ffield) (void)hipFree(c->ffield);
+    c->ffield = nullptr;
+    return LBM_OK;
+  }
+  if (c->eq != MAXWELL) return fail(LBM_EUNSUPPORTED, "the body force is implemented with the Maxwellian equilibrium");
+  if (c->literal) return fail(LBM_EUNSUPPORTED, "the body force runs with the deviation arithmetic");
+  if (c->transform == LBM_TRANSFORM_DENSE_MFMA) return fail(LBM_EUNSUPPORTED, "no body force in the MFMA ablation");
+  const size_t n = 3 * size_t(c->ncells);
+  std::vector<double> h(n);
+  if (is_device_ptr(F)) HIPCHECK(hipMemcpy(h.data(), F, n * sizeof(double), hipMemcpyDeviceToHost), "force copy");
+  else std::memcpy(h.data(), F, n * sizeof(double));
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(h[k])) return fail(LBM_EINVAL, "the force field must be finite");
+  const size_t eb = c->store == F64 ? sizeof(double) : sizeof(float);
+  if (!c->ffield) {
+    hipError_t e = hipMalloc(&c->ffield, n * eb);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      c->ffield = nullptr;
+      return fail(LBM_ENOMEM, "force field allocation");
+    }
+  }
+  if (c->store == F64) {
+    HIPCHECK(hipMemcpy(c->ffield, h.data(), n * sizeof(double), hipMemcpyHostToDevice), "force upload");
+  } else {
+    std::vector<float> hf(n);
+    for (size_t k = 0; k < n; ++k) hf[k] = float(h[k]);
+    HIPCHECK(hipMemcpy(c->ffield, hf.data(), n * sizeof(float), hipMemcpyHostToDevice), "force upload");
   }
   return LBM_OK;
 }
@@ -725,7 +780,8 @@ extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
   if (transform != LBM_TRANSFORM_CHIMERA && transform != LBM_TRANSFORM_DENSE_MFMA)
     return fail(LBM_EINVAL, "transform out of range");
   if (transform == LBM_TRANSFORM_DENSE_MFMA) {
-    if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL || c->space == SRT || c->literal)
+    if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL || c->space == SRT || c->literal ||
+        forced(c))
       return fail(LBM_EUNSUPPORTED,
                   "the MFMA ablation covers D3Q27 moment spaces, pull streaming, Maxwellian equilibrium, "
                   "deviation arithmetic");
@@ -1117,6 +1173,8 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   if (!common->zero_centered) return fail(LBM_EUNSUPPORTED, "the batched ensemble stores zero-centred populations");
   if (common->arithmetic != LBM_ARITH_DEVIATION)
     return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the deviation arithmetic");
+  if (common->force[0] != 0.0 || common->force[1] != 0.0 || common->force[2] != 0.0)
+    return fail(LBM_EUNSUPPORTED, "the batched ensemble runs without a body force");
   lbm_batch *b = new lbm_batch();
   b->p = *common;
   b->s = common->stencil;

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libpaper_lbm.so")
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
 STENCILS = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
 SPACES = {"raw": 0, "central": 1, "cumulant": 2, "srt": 3}
-EQUILIBRIA = {"maxwellian": 0, "swe": 1}
+EQUILIBRIA = {"maxwellian": 0, "swe": 1, "swe_maxwellian": 2}
 EQ_FORMS = {"default": 0, "absolute": 1, "delta": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 STREAMING = {"pull": 0, "aa": 1}
@@ -32,7 +32,7 @@ class LbmParams(ctypes.Structure):
                 ("gravity", c_double), ("nx", c_int64), ("ny", c_int64), ("nz", c_int64),
                 ("periodic", c_int * 3), ("storage", c_int), ("streaming", c_int),
                 ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p),
-                ("layout", c_int), ("arithmetic", c_int)]
+                ("layout", c_int), ("arithmetic", c_int), ("force", c_double * 3)]
 
 
 class LbmError(RuntimeError):
@@ -54,6 +54,7 @@ SIGNATURES = {
     "lbm_macroscopic": (c_int, [c_void_p, c_void_p, c_void_p]),
     "lbm_get_populations": (c_int, [c_void_p, c_void_p]),
     "lbm_set_populations": (c_int, [c_void_p, c_void_p]),
+    "lbm_set_force_field": (c_int, [c_void_p, c_void_p]),
     "lbm_diagnostics": (c_int, [c_void_p, POINTER(c_double)]),
     "lbm_synchronize": (c_int, [c_void_p]),
     "lbm_time": (c_int64, [c_void_p]),
@@ -124,7 +125,8 @@ def _dptr(a):
 
 
 def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", equilibrium="maxwellian",
-                eq_form="default", gravity=0.0, zero_centered=1, layout="auto", arithmetic="deviation"):
+                eq_form="default", gravity=0.0, zero_centered=1, layout="auto", arithmetic="deviation",
+                force=(0.0, 0.0, 0.0)):
     p = LbmParams()
     check(load().lbm_params_default(ctypes.byref(p)))
     p.stencil = STENCILS[stencil]
@@ -142,6 +144,8 @@ def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", e
     p.streaming = STREAMING[streaming]
     p.layout = LAYOUTS[layout]
     p.arithmetic = ARITHMETIC[arithmetic]
+    for d in range(3):
+        p.force[d] = float(force[d])
     return p
 
 
@@ -163,7 +167,7 @@ class Lattice:
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
                  equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto",
-                 zero_centered=True, arithmetic="deviation"):
+                 zero_centered=True, arithmetic="deviation", force=(0.0, 0.0, 0.0)):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
@@ -171,7 +175,8 @@ class Lattice:
         self.dims = tuple(int(v) for v in dims)
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
-                        zero_centered=1 if zero_centered else 0, layout=layout, arithmetic=arithmetic)
+                        zero_centered=1 if zero_centered else 0, layout=layout, arithmetic=arithmetic,
+                        force=force)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []
@@ -231,6 +236,16 @@ class Lattice:
         df = np.ascontiguousarray(df, dtype=np.float64)
         assert df.size == self.q * self.ncells
         check(self.lib.lbm_set_populations(self.ctx, _dptr(df)))
+
+    def lbm_set_force_field(self, F):
+        """F: (3, nz, ny, nx) FP64 body force per cell (numpy or torch), or None to remove it."""
+        if F is None:
+            check(self.lib.lbm_set_force_field(self.ctx, None))
+            return
+        if isinstance(F, np.ndarray):
+            F = np.ascontiguousarray(F, dtype=np.float64)
+            assert F.size == 3 * self.ncells
+        check(self.lib.lbm_set_force_field(self.ctx, _dptr(F)))
 
     def lbm_diagnostics(self, allow_nonfinite=False):
         out = (c_double * 6)()

@@ -250,6 +250,62 @@ def test_swe_lake_at_rest_is_fixed_point():
     np.testing.assert_allclose(out, df, rtol=0, atol=1e-15)
 
 
+def _swek(space, omega=0.7, g=0.1):
+    return O.Method("D2Q9", space, O.regularized_rates("D2Q9", omega), equilibrium="swe_maxwellian", gravity=g)
+
+
+@pytest.mark.parametrize("space", ["central", "cumulant"])
+def test_swe_maxwellian_equilibrium_moments(space):
+    """Venturi's equilibrium (continuous Maxwellian, c^2 = g h / 2) carries the shallow-water
+    fluxes: sum f = h, sum f xi = h u, sum f xi_a xi_b = g h^2 / 2 delta_ab + h u_a u_b, and
+    factorises over the axes: h f(ix, iy) = fx(ix) fy(iy)."""
+    g = 0.153
+    m = _swek(space, g=g)
+    st = m.st
+    rng = np.random.default_rng(5)
+    h = 0.5 + 2 * rng.random(6)
+    u = np.zeros((6, 3))
+    u[:, :2] = rng.uniform(-0.08, 0.08, (6, 2))
+    f = O.equilibrium_populations(m, h, u)
+    for n in range(6):
+        assert abs(sum(f[n, i] for i in range(9)) - h[n]) < 1e-15
+        for a in range(2):
+            assert abs(sum(f[n, i] * st.xi[i, a] for i in range(9)) - h[n] * u[n, a]) < 1e-15
+            for b in range(2):
+                got = sum(f[n, i] * st.xi[i, a] * st.xi[i, b] for i in range(9))
+                want = (0.5 * g * h[n] ** 2 if a == b else 0.0) + h[n] * u[n, a] * u[n, b]
+                assert abs(got - want) < 1e-14
+        tab = {(int(st.xi[i, 0]), int(st.xi[i, 1])): f[n, i] for i in range(9)}
+        fx = {a: sum(tab[(a, b)] for b in (-1, 0, 1)) for a in (-1, 0, 1)}
+        fy = {b: sum(tab[(a, b)] for a in (-1, 0, 1)) for b in (-1, 0, 1)}
+        for (a, b), v in tab.items():
+            assert abs(h[n] * v - fx[a] * fy[b]) < 1e-15
+
+
+def test_swe_maxwellian_central_and_cumulant_equilibria_agree():
+    m1, m2 = _swek("central"), _swek("cumulant")
+    rng = np.random.default_rng(6)
+    h = 1 + 0.3 * rng.random(4)
+    u = np.zeros((4, 3))
+    u[:, :2] = rng.uniform(-0.05, 0.05, (4, 2))
+    np.testing.assert_allclose(O.equilibrium_populations(m1, h, u), O.equilibrium_populations(m2, h, u),
+                               rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m1.f0, m2.f0, rtol=0, atol=1e-16)
+
+
+@pytest.mark.parametrize("space", ["central", "cumulant"])
+def test_swe_maxwellian_lake_at_rest_and_conservation(space):
+    m = _swek(space)
+    h = np.full((1, 6, 5), 1.3)
+    df = O.init_equilibrium(m, h, np.zeros((3, 1, 6, 5)))
+    np.testing.assert_allclose(O.step(m, df, 3), df, rtol=0, atol=1e-15)
+    cells = _state(m)
+    out = O.collide_cells(m, cells, "zc_absolute")
+    xi = m.st.xi.astype(float)
+    np.testing.assert_allclose(out.sum(axis=1), cells.sum(axis=1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(out @ xi, cells @ xi, rtol=0, atol=1e-15)
+
+
 def test_dam_break_rate_golden():
     g = json.load(open(GOLDEN))["dam_break_rate"]
     dx = g["domain_m"] / g["cells"]
@@ -359,3 +415,72 @@ def test_taylor_green_energy_decay_d3q27_cumulant():
     assert abs(rate / (4 * nu * k * k) - 1) < 1e-2
     d = O.diagnostics(m, df)
     assert abs(d[0] - d0[0]) < 1e-11 and np.abs(d[1:4] - d0[1:4]).max() < 1e-12
+
+
+# ---------------------------------------------------------------- body force (Guo's model)
+FORCE_CASES = [("D2Q9", "raw"), ("D2Q9", "cumulant"), ("D3Q19", "central"), ("D3Q27", "raw"),
+               ("D3Q27", "central"), ("D3Q27", "cumulant"), ("D3Q27", "srt")]
+
+
+@pytest.mark.parametrize("name,space", FORCE_CASES)
+def test_force_adds_exactly_F_of_momentum(name, space):
+    st = O.stencil(name)
+    if space == "srt":
+        om = np.full(st.q, 1.3)
+        om[st.conserved] = 0
+    else:
+        om = _general_rates(name, 9)
+    m = O.Method(name, space, om)
+    df = _state(m)
+    rng = np.random.default_rng(4)
+    F = rng.uniform(-1e-3, 1e-3, (df.shape[0], 3))
+    if st.d == 2:
+        F[:, 2] = 0
+    xi = st.xi.astype(float)
+    for form in _forms(space):
+        fin = df + m.f0 if form == "absolute" else df
+        out = O.collide_cells(m, fin, form, F)
+        np.testing.assert_allclose(out.sum(axis=1), fin.sum(axis=1), rtol=0, atol=2e-15)
+        np.testing.assert_allclose(out @ xi - fin @ xi, F, rtol=0, atol=2e-15)
+        if form != "absolute":
+            ref = O.collide_cells(m, df, O.default_form(m), F)
+            np.testing.assert_allclose(out, ref, rtol=0, atol=1e-14, err_msg=form)
+
+
+def test_uniform_force_accelerates_uniformly():
+    """A uniform state under a uniform force: u (Guo's velocity) grows by F / rho per step."""
+    m = O.Method("D3Q27", "cumulant", O.regularized_rates("D3Q27", 1.3))
+    rho = np.full((2, 3, 4), 1.02)
+    u = np.zeros((3, 2, 3, 4))
+    u[0] = 0.01
+    F = np.array([2e-4, -1e-4, 5e-5])
+    df = O.init_equilibrium(m, rho, u)
+    # the initial state has j = rho u, so Guo's velocity (j + F/2) / rho starts at u + F / (2 rho)
+    for t in range(1, 6):
+        df = O.step(m, df, 1, force=F)
+        r, uu = O.macroscopic(m, df, force=F)
+        want = np.array([0.01, 0.0, 0.0]) + F * t / 1.02 + 0.5 * F / 1.02
+        np.testing.assert_allclose(uu.reshape(3, -1).T, np.broadcast_to(want, (24, 3)), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
+def test_kolmogorov_flow_amplitude_second_order(space):
+    """Steady shear flow under F_x = F0 sin(k y): nu u'' + F = 0 gives u_x = F0 / (nu k^2) sin(k y).
+    Guo's model reproduces the amplitude with an error that falls as k^2 (sec. 2.1 source term)."""
+    om = O.regularized_rates("D2Q9", 0.8)
+    nu = O.omega_to_viscosity(0.8)
+    F0 = 1e-5
+    errs = []
+    for n, steps in ((12, 250), (24, 900)):
+        k = 2 * math.pi / n
+        y = np.arange(n)
+        F = np.zeros((3, 1, n, n))
+        F[0] = F0 * np.sin(k * y)[None, :, None]
+        m = O.Method("D2Q9", space, om)
+        df = O.init_equilibrium(m, np.ones((1, n, n)), np.zeros((3, 1, n, n)))
+        df = O.step(m, df, steps, force=F)
+        _, u = O.macroscopic(m, df, force=F)
+        amp = 2.0 / n * (u[0, 0, :, 0] * np.sin(k * y)).sum()  # projection on sin(k y)
+        errs.append(abs(amp / (F0 / (nu * k * k)) - 1.0))
+    assert errs[1] < 0.01
+    assert 3.0 < errs[0] / errs[1] < 5.0
