@@ -9,9 +9,10 @@
 // between the two transforms is the same collide_moments as the default kernel, so the
 // kernel measures the cost of replacing the Chimera with MFMA and LDS traffic.
 //
-// MFMA 16x16x4 operand layout (one value per lane for A and B, four for D):
-//   A[i][k] in lane i + 16 k,  B[k][j] in lane j + 16 k,  D[i][j] in lane j + 16 (i / 4),
-//   register i % 4.
+// MFMA 16x16x4 operand layout (one value per lane for A and B, four for D), checked on gfx950:
+//   A[i][k] in lane i + 16 k,  B[k][j] in lane j + 16 k;
+//   f32: D[i][j] in lane j + 16 (i / 4), register i % 4;
+//   f64: D[i][j] in lane j + 16 (i % 4), register i / 4.
 #pragma once
 
 #include "lbm_kernels.hpp"
@@ -24,12 +25,15 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ v4 mma(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  // row of D held by register r of a lane in row group lk = lane / 16
+  static __device__ __forceinline__ int drow(int lk, int r) { return 4 * lk + r; }
 };
 template <> struct Mfma<double> {
   typedef double v4 __attribute__((ext_vector_type(4)));
   static __device__ __forceinline__ v4 mma(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int drow(int lk, int r) { return 4 * r + lk; }
 };
 
 constexpr int MFMA_LDS_STRIDE = 65;  // padded row of 64 cells (avoids bank conflicts)
@@ -102,7 +106,7 @@ __device__ __forceinline__ void wave_dense27(CT *x, CT *lds, int lane) {
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 16 * rt + 4 * lk + r;
+        const int row = 16 * rt + Mfma<CT>::drow(lk, r);
         if (row < MFMA_ROWS) lds[row * MFMA_LDS_STRIDE + 16 * ct + li] = acc[rt][ct][r];
       }
   __syncthreads();
