@@ -32,16 +32,16 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
 SBYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, layout):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel sources; else None."""
+    current kernel sources and the same storage layout; else None."""
     path = TRAFFIC_FILE.format(workload=workload)
     if not os.path.exists(path):
         return None
     from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
     with open(path) as f:
         t = json.load(f)
-    if t.get("kernel_source_sha") != kernel_source_hash():
+    if t.get("kernel_source_sha") != kernel_source_hash() or t.get("layout") != layout:
         return None
     return t.get("bytes_per_launch")
 
@@ -57,12 +57,11 @@ def workload_fields(name, cfg, n):
 def workload_rates(cfg, general=False):
     """Regularized rates of the workload; with general=True every rate of order >= 3 is 1.3
     instead of 1, which selects the general (non-regularized) kernels."""
-    import oracle as O
-    om = O.regularized_rates(cfg["stencil"], cfg["omega_shear"])
+    from paper_2211_02435_amd import lbm
+    om = lbm.regularized_rates(cfg["stencil"], cfg["omega_shear"])
     if general:
-        st = O.stencil(cfg["stencil"])
-        for k, poly in enumerate(st.basis):
-            if sum(next(iter(poly))) >= 3:
+        for k, order in enumerate(lbm.BASIS_ORDERS[cfg["stencil"]]):
+            if order >= 3:
                 om[k] = 1.3
     return om
 
@@ -70,11 +69,10 @@ def workload_rates(cfg, general=False):
 def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout, transform="chimera",
                 general=False):
     """Run one box: init, autotune, warm-up, record the graph, time `steps` sweeps."""
-    import oracle as O
     import torch
     stencil, space = cfg["stencil"], cfg["space"]
     om = workload_rates(cfg, general)
-    q = O.stencil(stencil).q
+    q = lbm.Q[stencil]
     kw = {}
     if cfg.get("equilibrium") == "swe":
         kw = {"equilibrium": "swe", "gravity": cfg["gravity"]}
@@ -104,17 +102,16 @@ def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, stream
            "bytes_per_lup": 2 * q * SBYTES[storage],
            "launch_bx_by_swizzle_vec_lds": list(lat.lbm_get_launch()) + [int(lat.lbm_get_vectorized()),
                                                                         lat.lbm_get_lds_reserve()],
-           "transform": lat.lbm_get_transform()}
+           "transform": lat.lbm_get_transform(), "layout": lat.lbm_get_layout()}
     return lat, res
 
 
 def measure_batch(lbm, steps, warmup):
     """The ensemble of 256 D3Q27 central-moment boxes (FP32), one launch per step, graph."""
-    import oracle as O
     import torch
     boxes = W.batch_ensemble(256, seed=0)
     dims = [(b["edge"],) * 3 for b in boxes]
-    rates = [O.regularized_rates("D3Q27", b["omega_shear"]) for b in boxes]
+    rates = [lbm.regularized_rates("D3Q27", b["omega_shear"]) for b in boxes]
     fields = [W.batch_fields(b) for b in boxes]
     rho = np.concatenate([f[0].ravel() for f in fields])
     u = np.concatenate([f[1].ravel() for f in fields])
@@ -278,13 +275,13 @@ def main():
         "dtype": main_st,
         "data": "synthetic initial fields (Taylor-Green vortex / Gaussian water bumps)",
         "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
-                   "layout": args.layout, "streaming": args.streaming, "transform": args.transform,
+                   "layout": r.get("layout", args.layout), "streaming": args.streaming, "transform": args.transform,
                    "rates": args.rates,
                    "launch_bx_by_swizzle_vec_lds": r["launch_bx_by_swizzle_vec_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
-                     "traffic": measured_traffic(name) if (n == cfg["dims"][0] and main_st == "f32"
-                                                           and args.layout == "auto" and args.streaming == "pull"
+                     "traffic": measured_traffic(name, r.get("layout")) if (n == cfg["dims"][0] and main_st == "f32"
+                                                           and args.streaming == "pull"
                                                            and args.transform == "chimera"
                                                            and args.rates == "regularized") else None,
                      "kernel": "sweep_kernel<%s, %s, %s, %s, %s>" % (cfg["stencil"], cfg["space"], args.rates,

@@ -115,8 +115,8 @@ typedef enum { LBM_ARITH_DEVIATION = 0, LBM_ARITH_LITERAL = 1 } lbm_arithmetic;
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
- * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: PLANES for F32 and
- * F16 storage, ROWS for F64 (the faster layout measured for each on MI355X). */
+ * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS (the faster
+ * layout measured on MI355X for F64, F32 and F16 storage). */
 typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 } lbm_layout;
 
 typedef struct {
@@ -244,6 +244,10 @@ int lbm_get_vectorized(const lbm_ctx *ctx);
 typedef enum { LBM_TRANSFORM_CHIMERA = 0, LBM_TRANSFORM_DENSE_MFMA = 1 } lbm_transform;
 lbm_status lbm_set_transform(lbm_ctx *ctx, int transform);
 int lbm_get_transform(const lbm_ctx *ctx);
+
+/* The layout the context's buffers use (LBM_LAYOUT_PLANES or LBM_LAYOUT_ROWS; AUTO resolved),
+ * or -1 for a NULL context. */
+int lbm_get_layout(const lbm_ctx *ctx);
 
 /* Dynamic LDS reserved by every sweep block (0 .. 65536 bytes; the sweep itself uses none):
  * caps the resident blocks per CU (160 KB of LDS each), i.e. the number of waves streaming

@@ -39,7 +39,7 @@ size_t plane_elems(const lbm_params *p) {
 
 int resolve_layout(const lbm_params *p) {
   if (p->layout == LBM_LAYOUT_PLANES || p->layout == LBM_LAYOUT_ROWS) return p->layout;
-  return p->storage == LBM_STORE_F64 ? LBM_LAYOUT_ROWS : LBM_LAYOUT_PLANES;
+  return LBM_LAYOUT_ROWS;
 }
 
 // element strides of population i, z and y (x has stride 1) and elements per buffer

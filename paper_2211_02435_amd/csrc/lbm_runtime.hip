@@ -795,6 +795,8 @@ extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
 
 extern "C" int lbm_get_transform(const lbm_ctx *c) { return c ? c->transform : -1; }
 
+extern "C" int lbm_get_layout(const lbm_ctx *c) { return c ? c->layout : -1; }
+
 extern "C" lbm_status lbm_set_lds_reserve(lbm_ctx *c, int bytes) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   if (bytes < 0 || bytes > 65536) return fail(LBM_EINVAL, "LDS reserve must be in [0, 65536] bytes");
@@ -1089,6 +1091,7 @@ struct lbm_batch {
   std::map<std::pair<int64_t, int>, hipGraphExec_t> gcache;
   double *staging = nullptr;
   size_t staging_doubles = 0;
+  int swz = 1;  // XCD-ordered tiles (LBM_BATCH_SWIZZLE=0 switches it off)
 };
 
 namespace lbm {
@@ -1107,6 +1110,7 @@ static lbm_status batch_one_step(lbm_batch *b) {
     a.boxes = b->boxes_d;
     a.tile_box = b->tile_box_d;
     a.relax = static_cast<const Relax<CT> *>(b->relax_d);
+    a.swizzle = b->swz;
     void *args[] = {&a};
     return hipLaunchKernel(fn, dim3(b->ntiles), dim3(BATCH_THREADS), args, 0, b->stream);
   };
@@ -1181,6 +1185,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   b->q = stencil_q(b->s);
   b->d = 3;
   b->space = internal_space(common->space);
+  if (const char *env = std::getenv("LBM_BATCH_SWIZZLE")) b->swz = env[0] == '0' ? 0 : 1;
   b->store = common->storage;
   b->elem = storage_bytes(b->store);
   b->nboxes = nboxes;

@@ -23,6 +23,26 @@ STREAMING = {"pull": 0, "aa": 1}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+# order of every polynomial of the bases documented in lbm.h (one rate per entry of omegas)
+BASIS_ORDERS = {
+    "D2Q9": [0, 1, 1, 2, 2, 2, 3, 3, 4],
+    "D3Q19": [0, 1, 1, 1] + [2] * 6 + [3] * 6 + [4] * 3,
+    "D3Q27": [0, 1, 1, 1] + [2] * 6 + [3] * 6 + [3] + [4] * 3 + [4] * 3 + [5] * 3 + [6],
+}
+# positions of the shear polynomials (xy, xz, yz, x2-y2, x2-z2) and of the trace x2+y2(+z2)
+SHEAR = {"D2Q9": [3, 4], "D3Q19": [4, 5, 6, 7, 8], "D3Q27": [4, 5, 6, 7, 8]}
+TRACE = {"D2Q9": 5, "D3Q19": 9, "D3Q27": 9}
+
+
+def regularized_rates(stencil, omega_shear, omega_bulk=1.0):
+    """Rates of an "R-" method (sec. 4.3) in the basis order of lbm.h: omega_shear on the shear
+    polynomials, omega_bulk on the trace, 1 on every higher-order polynomial, 0 on the conserved
+    ones (ignored by the library)."""
+    om = np.ones(Q[stencil])
+    om[[k for k, o in enumerate(BASIS_ORDERS[stencil]) if o < 2]] = 0.0
+    om[SHEAR[stencil]] = omega_shear
+    om[TRACE[stencil]] = omega_bulk
+    return om
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
@@ -65,6 +85,7 @@ SIGNATURES = {
     "lbm_get_vectorized": (c_int, [c_void_p]),
     "lbm_set_transform": (c_int, [c_void_p, c_int]),
     "lbm_get_transform": (c_int, [c_void_p]),
+    "lbm_get_layout": (c_int, [c_void_p]),
     "lbm_set_lds_reserve": (c_int, [c_void_p, c_int]),
     "lbm_get_lds_reserve": (c_int, [c_void_p]),
     "lbm_autotune": (c_int, [c_void_p]),
@@ -279,6 +300,9 @@ class Lattice:
 
     def lbm_set_transform(self, transform):
         check(self.lib.lbm_set_transform(self.ctx, {"chimera": 0, "dense_mfma": 1}[transform]))
+
+    def lbm_get_layout(self):
+        return {1: "planes", 2: "rows"}[int(self.lib.lbm_get_layout(self.ctx))]
 
     def lbm_get_transform(self):
         return {0: "chimera", 1: "dense_mfma"}[int(self.lib.lbm_get_transform(self.ctx))]

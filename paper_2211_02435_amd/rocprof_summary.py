@@ -4,7 +4,7 @@
       per-kernel calls, total and average duration (the --kernel-trace --stats view)
 
   python -m paper_2211_02435_amd.rocprof_summary traffic --fetch <db> --write <db>
-      --kernel <substring> --copy-bytes <bytes> --workload <name> [--out <json>]
+      --kernel <substring> --copy-bytes <bytes> --workload <name> [--layout planes|rows] [--out <json>]
       HBM bytes per launch of the kernel from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
       each scaled by what the same counter reads for the plain copy kernel of known size,
       together with the hash of the kernel sources the counters were taken on.
@@ -75,7 +75,7 @@ def counter_per_dispatch(db, counter):
     return out
 
 
-def traffic(fetch_db, write_db, kernel, copy_bytes, workload):
+def traffic(fetch_db, write_db, kernel, copy_bytes, workload, layout=None):
     f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
     w = counter_per_dispatch(write_db, "WRITE_SIZE")
 
@@ -89,7 +89,7 @@ def traffic(fetch_db, write_db, kernel, copy_bytes, workload):
     f_copy, w_copy = pick(f, "copy_kernel"), pick(w, "copy_kernel")
     f_k, w_k = pick(f, kernel), pick(w, kernel)
     sf, sw = copy_bytes / (f_copy * 1024.0), copy_bytes / (w_copy * 1024.0)
-    return {"workload": workload, "kernel_match": kernel, "kernel_source_sha": kernel_source_hash(),
+    return {"workload": workload, "layout": layout, "kernel_match": kernel, "kernel_source_sha": kernel_source_hash(),
             "fetch_kib_per_launch_raw": f_k, "write_kib_per_launch_raw": w_k,
             "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy, "copy_bytes_each_way": copy_bytes,
             "fetch_scale": sf, "write_scale": sw,
@@ -109,6 +109,7 @@ def main(argv=None):
     t.add_argument("--kernel", required=True)
     t.add_argument("--copy-bytes", type=float, required=True)
     t.add_argument("--workload", required=True)
+    t.add_argument("--layout", default=None, help="storage layout of the profiled run (planes / rows)")
     t.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
@@ -118,7 +119,7 @@ def main(argv=None):
             print("%-110s %6d %12.1f %10.1f %10.1f %10.1f" % (r["kernel"][:110], r["calls"], r["total_us"],
                                                                r["avg_us"], r["min_us"], r["max_us"]))
     else:
-        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload)
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload, a.layout)
         txt = json.dumps(res, indent=1)
         if a.out:
             with open(a.out, "w") as f:
