@@ -115,8 +115,8 @@ typedef enum { LBM_ARITH_DEVIATION = 0, LBM_ARITH_LITERAL = 1 } lbm_arithmetic;
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
- * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS (the faster
- * layout measured on MI355X for F64, F32 and F16 storage). */
+ * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS, except
+ * PLANES for F64 storage with AA streaming (the faster layout measured on MI355X). */
 typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 } lbm_layout;
 
 typedef struct {

@@ -422,18 +422,42 @@ template <class T>
 LBM_HD void swe_feq_dev(T *g9, T dh, T h, T ux, T uy, T grav) {
   const T h2m1 = dh * (T(2) + dh);
   const T uu = ux * ux + uy * uy;
+  const T a = grav * h2m1 * T(1.0 / 6.0);  // g (h^2 - 1) / 6
+  const T d = a - h * uu * T(1.0 / 6.0);   // ... - h u.u / 6
+  const T b = h * T(1.0 / 3.0), c = T(0.5) * h;
   sfor<9>([&](auto I) {
     constexpr int i = decltype(I)::value;
     constexpr int cx = vel9(i, 0), cy = vel9(i, 1);
     constexpr int gi = (cx + 1) + 3 * (cy + 1);
     if constexpr (i == 0) {
-      g9[gi] = dh - T(5) / T(6) * grav * h2m1 - T(2) / T(3) * h * uu;
+      g9[gi] = dh - T(5) * a - T(2.0 / 3.0) * h * uu;
     } else {
       constexpr T lam = (cx != 0 && cy != 0) ? T(0.25) : T(1);
-      T xu = T(cx) * ux + T(cy) * uy;
-      g9[gi] = lam * (grav * h2m1 / T(6) + h * (xu / T(3) + T(0.5) * xu * xu - uu / T(6)));
+      T xu = T(0);
+      if constexpr (cx != 0) xu = cx > 0 ? xu + ux : xu - ux;
+      if constexpr (cy != 0) xu = cy > 0 ? xu + uy : xu - uy;
+      g9[gi] = lam * (d + xu * (b + c * xu));
     }
   });
+}
+
+// Raw moments of Zhou's equilibrium as deviations about its rest state (h = 1, u = 0), in
+// closed form: h, h u, g (h^2 - 1) / 2 + h u_a^2, h ux uy, h u_b / 3 (x^2 y and x y^2),
+// g (h^2 - 1) / 6 + h u.u / 3 (x^2 y^2); the same as M applied to swe_feq_dev.
+template <class T>
+LBM_HD void swe_meq_dev(T *m, T dh, T h, const T *u, T grav) {
+  const T ux = u[0], uy = u[1];
+  const T h2m1 = dh * (T(2) + dh);
+  const T h3 = h * T(1.0 / 3.0);
+  m[mono(0, 0, 0)] = dh;
+  m[mono(1, 0, 0)] = h * ux;
+  m[mono(0, 1, 0)] = h * uy;
+  m[mono(2, 0, 0)] = T(0.5) * grav * h2m1 + h * ux * ux;
+  m[mono(0, 2, 0)] = T(0.5) * grav * h2m1 + h * uy * uy;
+  m[mono(1, 1, 0)] = h * ux * uy;
+  m[mono(2, 1, 0)] = h3 * uy;
+  m[mono(1, 2, 0)] = h3 * ux;
+  m[mono(2, 2, 0)] = grav * h2m1 * T(1.0 / 6.0) + h3 * (ux * ux + uy * uy);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -517,8 +541,8 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   // equilibrium moments (deviation form)
   T meq[G];
   if constexpr (EQ == SWE) {
-    swe_feq_dev(meq, drho, rho, u[0], u[1], grav);
-    chimera_forward<S>(meq);
+    static_assert(S == D2Q9, "the shallow-water equilibria are two-dimensional");
+    swe_meq_dev(meq, drho, rho, u, grav);
   } else if constexpr (EQ == SWEK) {
     static_assert(S == D2Q9, "the shallow-water equilibria are two-dimensional");
     swek_meq_dev(meq, drho, rho, u, grav);
