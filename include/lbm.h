@@ -99,7 +99,11 @@ typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_sto
 /* PULL: two arrays, each step gathers f_i(x) from x - xi_i.  AA: one array, in place
  * (even steps read and write the cell's own slots, odd steps read from x - xi_i and write to
  * x + xi_i); sec. 4.4. */
-typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1 } lbm_streaming;
+/* ESOTERIC_PULL: one array, in place (sec. 4.4): every step a cell touches its own slots and
+ * the neighbours x + xi of one direction of each opposite pair (the odd indices); population i
+ * of an odd direction (and the rest) is kept at the cell, that of an even direction at
+ * x - xi, in slot opp(i) after an even number of steps and in slot i after an odd number. */
+typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1, LBM_STREAM_ESOTERIC_PULL = 2 } lbm_streaming;
 
 /* How the collision's arithmetic is organised.  DEVIATION: every intermediate is a deviation
  * from the background (raw, central and cumulant moments of df, the equilibrium deviation

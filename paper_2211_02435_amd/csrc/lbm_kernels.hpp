@@ -1,7 +1,8 @@
 // HIP kernels of the lattice Boltzmann library (gfx950).
 //
 // sweep_kernel   fused stream + collide over every cell (eq. LbUpdateScheme, sec. 2.1, with
-//                the collision of sec. 2.2) for the pull and AA patterns (sec. 4.4)
+//                the collision of sec. 2.2) for the pull, AA and Esoteric-Pull patterns
+//                (sec. 4.4)
 // init_kernel    zero-centred equilibrium initialisation in FP64 (sec. 2.4)
 // export_kernel / import_kernel   canonical df(t) <-> storage layout
 // macro_kernel   density and velocity of df(t) (eq. DensityAndVelocityFromDeviation)
@@ -13,6 +14,16 @@
 // coordinates (integer selects only).  Stores are non-temporal: every population written in
 // a sweep is read again only in the next sweep, after the whole 2 Q sizeof(ST) ncells bytes
 // have streamed through the caches.
+//
+// In-place patterns (one buffer; each step every cell reads and writes the same locations, so
+// the sweep is race-free).  Directions come in opposite pairs (i odd, opp(i) = i + 1).
+//   AA:            even steps use the cell's own slots (reading slot i, writing slot opp(i));
+//                  odd steps read slot opp(i) at x - xi and write slot i at x + xi.
+//   Esoteric Pull: every step touches the own cell and the neighbours x + xi of the odd
+//                  directions only.  Odd i and the rest population live at the own cell,
+//                  even i at x - xi; on even steps population i is found in slot opp(i), on
+//                  odd steps in slot i.  After the collision odd directions are written to
+//                  x + xi, the others stay, the slot index flipping with the parity.
 #pragma once
 
 #include "lbm_device.hpp"
@@ -198,8 +209,17 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
     } else if constexpr (PAT == AA_EVEN) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
-    } else {
+    } else if constexpr (PAT == AA_ODD) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+    } else {
+      // Esoteric Pull: odd directions (and the rest) sit at the own node, their opposites at
+      // x - xi; even steps find every population in the opposite slot, odd steps in its own
+      constexpr int slot = PAT == ESO_EVEN ? L::opp(i) : i;
+      if constexpr (i == 0 || (i & 1)) {
+        g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(slot) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
+      } else {
+        g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(slot) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+      }
     }
   });
 
@@ -228,8 +248,17 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else if constexpr (PAT == AA_EVEN) {
       stp(a.dst, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
-    } else {
+    } else if constexpr (PAT == AA_ODD) {
       stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
+    } else {
+      // odd directions go to x + xi, the others stay; the even step keeps the slot index,
+      // the odd step writes the opposite slot (the same locations the loads read)
+      constexpr int slot = PAT == ESO_EVEN ? i : L::opp(i);
+      if constexpr (i != 0 && (i & 1)) {
+        stp(a.dst, (uint64_t(slot) * a.L.ps) + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
+      } else {
+        stp(a.dst, (uint64_t(slot) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
+      }
     }
   });
 }
@@ -361,9 +390,20 @@ __device__ __forceinline__ void canon_addr(const Nbr<Lat<S>::D> &nb, const Strid
   } else if constexpr (GM == G_SHIFTED) {
     uni = uint64_t(i) * L.ps + nb.zpart(cz, -1);
     lane = nb.lane(cx, cy, -1);
-  } else {
+  } else if constexpr (GM == G_AA_ODD) {
     uni = uint64_t(Lat<S>::opp(i)) * L.ps + nb.zpart(cz, -1);
     lane = nb.lane(cx, cy, -1);
+  } else {
+    // Esoteric Pull: slot opp(i) (even times) or i (odd times); odd i at the own node,
+    // even i > 0 at x - xi
+    const int slot = GM == G_ESO_EVEN ? Lat<S>::opp(i) : i;
+    if (i == 0 || (i & 1)) {
+      uni = uint64_t(slot) * L.ps + nb.zpart(0, 1);
+      lane = nb.lane(0, 0, 1);
+    } else {
+      uni = uint64_t(slot) * L.ps + nb.zpart(cz, -1);
+      lane = nb.lane(cx, cy, -1);
+    }
   }
 }
 
@@ -385,7 +425,8 @@ __device__ __forceinline__ void gather_canon(const FieldArgs &a, const CellPos &
   });
 }
 
-// df(0) = f_eq(rho, u) - f0, written in layout GM (G_SHIFTED for pull, G_NATURAL for AA)
+// df(0) = f_eq(rho, u) - f0, written in layout GM (G_SHIFTED for pull, G_NATURAL for AA,
+// G_ESO_EVEN for Esoteric Pull)
 template <int S, int SP, int EQ, int GM, class ST>
 __global__ void __launch_bounds__(256) init_kernel(FieldArgs a) {
   using L = Lat<S>;

@@ -288,7 +288,8 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     src = c->buf[c->cur];
     dst = c->buf[c->cur ^ 1];
   } else {
-    pat = (c->t % 2 == 0) ? AA_EVEN : AA_ODD;
+    if (c->pattern == LBM_STREAM_AA) pat = (c->t % 2 == 0) ? AA_EVEN : AA_ODD;
+    else pat = (c->t % 2 == 0) ? ESO_EVEN : ESO_ODD;
     src = c->buf[0];
     dst = c->buf[0];
   }
@@ -305,7 +306,7 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     if (!fn) return fail(LBM_EUNSUPPORTED, "no MFMA ablation kernel for this method");
     HIPCHECK(launch_sweep_lds(c, fn, src, dst, mfma_lds_bytes(c)), "sweep launch");
   } else {
-    const bool vec = c->vec && pat != AA_ODD && vec_ok(c, c->bx);
+    const bool vec = c->vec && (pat == PULL || pat == AA_EVEN) && vec_ok(c, c->bx);
     const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, vec), "sweep launch");
@@ -317,7 +318,8 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
 
 static int state_gather_mode(const lbm_ctx *c) {
   if (c->pattern == LBM_STREAM_PULL) return G_SHIFTED;
-  return (c->t % 2 == 0) ? G_NATURAL : G_AA_ODD;
+  if (c->pattern == LBM_STREAM_AA) return (c->t % 2 == 0) ? G_NATURAL : G_AA_ODD;
+  return (c->t % 2 == 0) ? G_ESO_EVEN : G_ESO_ODD;
 }
 static void *state_buffer(const lbm_ctx *c) { return c->pattern == LBM_STREAM_PULL ? c->buf[c->cur] : c->buf[0]; }
 
@@ -500,7 +502,7 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const 
   }
   c->t = 0;
   c->cur = 0;
-  const int gm = c->pattern == LBM_STREAM_PULL ? G_SHIFTED : G_NATURAL;
+  const int gm = c->pattern == LBM_STREAM_PULL ? G_SHIFTED : (c->pattern == LBM_STREAM_AA ? G_NATURAL : G_ESO_EVEN);
   const int sp_init = c->eq == SWE ? CENTRAL : c->space;
   FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
   a.rho_in = drho;
@@ -727,14 +729,15 @@ extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 extern "C" lbm_status lbm_set_time(lbm_ctx *c, int64_t t) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
-  if (c->pattern == LBM_STREAM_AA && (t % 2) != (c->t % 2)) {
+  if (c->pattern != LBM_STREAM_PULL && (t % 2) != (c->t % 2)) {
     // odd and even times use different layouts: move the state pair by pair (slots i and
     // opp(i) only exchange with each other) from the old layout to the new one
     const size_t n = c->ncells;
     lbm_status s = ensure_staging(c, 2 * n);
     if (s != LBM_OK) return s;
     const int gm_old = state_gather_mode(c);
-    const int gm_new = (t % 2 == 0) ? G_NATURAL : G_AA_ODD;
+    const int gm_new = c->pattern == LBM_STREAM_AA ? ((t % 2 == 0) ? G_NATURAL : G_AA_ODD)
+                                                    : ((t % 2 == 0) ? G_ESO_EVEN : G_ESO_ODD);
     for (int i0 = 0; i0 < c->q; i0 = (i0 == 0 ? 1 : i0 + 2)) {
       FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
       a.pop = c->staging;
@@ -919,10 +922,10 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
           if (cby > 1 && cby / 2 >= c->ny) continue;
           cand.push_back({cbx, cby, cs, cv});
         }
-  // the sweep must leave the state unchanged: pull writes only the other buffer; AA runs
-  // on a copy of the buffer that is restored afterwards
+  // the sweep must leave the state unchanged: pull writes only the other buffer; the in-place
+  // patterns run on a copy of the buffer that is restored afterwards
   void *saved = nullptr;
-  if (c->pattern == LBM_STREAM_AA) {
+  if (c->pattern != LBM_STREAM_PULL) {
     hipError_t e = hipMalloc(&saved, c->buf_bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();

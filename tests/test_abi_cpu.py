@@ -64,6 +64,7 @@ def test_valid_parameter_sets():
     b32 = lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f32"))
     assert b32 % (2 * 27 * 256) == 0 and b32 >= 2 * 27 * 256 * 4
     b16 = lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f16", streaming="aa"))
+    assert lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f16", streaming="esoteric")) == b16
     assert b16 % (27 * 256) == 0 and b16 >= 27 * 240 * 2
 
 
@@ -87,6 +88,7 @@ def test_valid_parameter_sets():
     (dict(stencil="D3Q19", space="raw", arithmetic="literal"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", storage="f16"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="aa"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="raw", arithmetic="literal", streaming="esoteric"), lbm.LBM_EUNSUPPORTED),
     (dict(space="cumulant", arithmetic="literal", eq_form="delta"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_invalid_parameter_sets(kw, code):
