@@ -117,6 +117,12 @@ typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1, LBM_STREAM_ESOTERIC_PULL 
  * covers D2Q9 and D3Q27, F64 and F32 storage, pull streaming, the Maxwellian equilibrium. */
 typedef enum { LBM_ARITH_DEVIATION = 0, LBM_ARITH_LITERAL = 1 } lbm_arithmetic;
 
+/* Source-term model of a body force (sec. 2.1 cites both): GUO (Guo, Zheng, Shi):
+ * S_i = w_i [(xi_i - u) / cs2 + (xi_i . u) xi_i / cs4] . F;  HE (He, Shan, Doolen):
+ * S_i = (xi_i - u) . F f_eq_i / (rho cs2) with the method's equilibrium populations.  Both
+ * shift the equilibrium velocity to u = (j + F/2) / rho and add (I - S/2) T(S). */
+typedef enum { LBM_FORCE_GUO = 0, LBM_FORCE_HE = 1 } lbm_force_model;
+
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
  * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS, except
@@ -141,8 +147,9 @@ typedef struct {
   void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
   int layout;             /* lbm_layout of the device population buffers                      */
   int arithmetic;         /* lbm_arithmetic of the collision                                  */
-  double force[3];        /* constant body force per cell and step (lattice units), Guo's     */
-                          /* model; {0, 0, 0} for none.  See lbm_set_force_field.             */
+  double force[3];        /* constant body force per cell and step (lattice units);           */
+                          /* {0, 0, 0} for none.  See lbm_set_force_field.                    */
+  int force_model;        /* lbm_force_model of any body force                                */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;
@@ -194,7 +201,8 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
  * recording cost stays out of a timed region.  No effect for n < 2 or with graphs off. */
 lbm_status lbm_graph_prepare(lbm_ctx *ctx, int64_t n);
 
-/* Body force field (sec. 2.1 source term, eq. MrtUpdateGeneral's q^F) with Guo's model:
+/* Body force field (sec. 2.1 source term, eq. MrtUpdateGeneral's q^F) with the model of
+ * params.force_model (Guo's by default):
  * F[d * ncells + cell], d = 0..2, FP64, host or device pointer, copied (in the compute
  * precision) and added to the constant params.force in every following step; NULL removes
  * it.  With a force the equilibrium velocity is u = (j + F/2) / rho, the source's moments in

@@ -39,10 +39,11 @@ tests/test_oracle_*.py check it against something other than itself):
         pin: moments of orders 0..2 are rho, rho u, rho (cs2 delta + u u) on every stencil;
              on the tensor-product stencils D2Q9 / D3Q27 one SRT collision equals the
              raw-moment collision with all rates omega (moment-space BGK)
-  guo_source / force         source term f^F of eq. LbUpdateScheme and q^F of
+  guo_source / he_source     source term f^F of eq. LbUpdateScheme and q^F of
                              eq. MrtUpdateGeneral (sec. 2.1, 2.2) with Guo's force model: the
                              equilibrium velocity u = (j + F/2) / rho, q^F the source's moments
-                             in the collision space at u, weighted by (I - S/2)
+                             in the collision space at u, weighted by (I - S/2); He's model
+                             weights (xi - u) . F by the equilibrium populations instead
         pin: every cell gains exactly F of momentum and no mass; a uniform force accelerates a
              uniform state by F / rho per step; the steady Kolmogorov flow under
              F_x = F0 sin(k y) has the analytic amplitude F0 / (nu k^2) to second order
@@ -398,13 +399,15 @@ class Method:
     Rates of the conserved polynomials (1, x, y, z) are ignored (pass-through).  'srt' works
     on the populations themselves with one rate, the common value of the non-conserved rates."""
 
-    def __init__(self, stencil_name, space, omegas, equilibrium="maxwellian", gravity=None):
+    def __init__(self, stencil_name, space, omegas, equilibrium="maxwellian", gravity=None, force_model="guo"):
         self.st = stencil(stencil_name)
         self.space = space
         self.omegas = np.asarray(omegas, dtype=np.float64)
         assert self.omegas.shape == (self.st.q,)
         self.equilibrium = equilibrium
         self.gravity = gravity
+        assert force_model in ("guo", "he")
+        self.force_model = force_model
         if space == "srt":
             assert equilibrium == "maxwellian"
             rest = self.omegas[self.st.d + 1:]
@@ -502,6 +505,16 @@ def guo_source(st, u, F):
     return st.w[None, :] * ((xF - uF) / CS2 + xu * xF / (CS2 * CS2))
 
 
+def he_source(st, u, F, rho, feq):
+    """He's forcing populations (n, q): S_i = (xi_i - u) . F f_eq_i / (rho cs2), with feq the
+    method's absolute equilibrium populations (the source term of sec. 2.1 in the model of He,
+    Shan and Doolen)."""
+    xi = st.xi.astype(np.float64)
+    xF = F @ xi.T
+    uF = (u * F).sum(axis=1)[:, None]
+    return (xF - uF) * feq / (CS2 * rho[:, None])
+
+
 def macroscopic_from_delta(method, df_cells):
     """eq. DensityAndVelocityFromDeviation: rho = rho0 + sum df, u = sum df xi / rho."""
     st = method.st
@@ -527,7 +540,11 @@ def _collide_forced(m, f_cells, form, F):
         rho = 1.0 + f_cells.sum(axis=1)
         j = f_cells @ xi
     u = (j + 0.5 * F) / rho[:, None]
-    qFw = m.weighted_force(m.force_moments(guo_source(st, u, F), u))
+    if m.force_model == "he":
+        S = he_source(st, u, F, rho, equilibrium_populations(m, rho, u))
+    else:
+        S = guo_source(st, u, F)
+    qFw = m.weighted_force(m.force_moments(S, u))
     if m.space == "cumulant":
         if form == "delta":
             raise ValueError("the cumulant transform is nonlinear: no delta-equilibrium (sec. 3)")

@@ -512,6 +512,28 @@ LBM_HD void guo_source(T *src, const T *u, const T *F) {
   });
 }
 
+// He's forcing populations (He, Shan and Doolen): S_i = (xi_i - u) . F f_eq_i / (rho cs2),
+// with f_eq the method's equilibrium populations, here w_i + fe_i (fe: their deviations)
+template <int S, class T>
+LBM_HD void he_source(T *src, const T *fe, const T *u, const T *F, T rinv) {
+  using L = Lat<S>;
+  sfor<L::G>([&](auto E) { src[E] = T(0); });
+  const T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int gi = L::gidx(i);
+    T xF = T(0);
+    sfor<3>([&](auto Dd) {
+      constexpr int d = decltype(Dd)::value;
+      if constexpr (L::c(i, d) > 0) xF += F[d];
+      else if constexpr (L::c(i, d) < 0) xF -= F[d];
+    });
+    src[gi] = T(3) * (xF - uF) * (T(L::w(i)) + fe[gi]) * rinv;
+  });
+}
+
+enum ForceModel { FORCE_GUO = 0, FORCE_HE = 1 };
+
 // ---------------------------------------------------------------------------------------
 // the collision in moment space: m holds dm = M df (exponent-grid order) on entry and the
 // post-collision dm* on exit.  Missing monomials (D3Q19) leave as zero.
@@ -521,7 +543,7 @@ LBM_HD void guo_source(T *src, const T *u, const T *F) {
 // moments weighted by (I - P^-1 S P / 2) = (I + B) / 2 are added in the collision space
 // (raw moments, or central moments for the central and cumulant spaces); momentum grows by F.
 template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
-LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullptr) {
+LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullptr, int fmodel = FORCE_GUO) {
   static_assert(!(FORCE && REG), "the forced collision uses the general kernel");
   constexpr int D = Lat<S>::D;
   constexpr int G = Lat<S>::G;
@@ -573,7 +595,14 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   auto add_force = [&](T *vv, bool central) {
     if constexpr (FORCE) {
       T fs[G];
-      guo_source<S>(fs, u, F);
+      if (fmodel == FORCE_HE) {
+        T fe[G];  // equilibrium populations (deviations) of the method at the shifted u
+        sfor<G>([&](auto E) { fe[E] = meq[E]; });
+        chimera_inverse<S>(fe);
+        he_source<S>(fs, fe, u, F, rinv);
+      } else {
+        guo_source<S>(fs, u, F);
+      }
       chimera_forward<S>(fs);
       if (central) binomial<S>(fs, -u[0], -u[1], -u[2]);
       T wfs[G];
@@ -636,7 +665,7 @@ LBM_HD void srt_feq_dev(T *feq, T drho, T rho, const T *u) {
 }
 
 template <int S, class T, bool FORCE = false>
-LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr) {
+LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr, int fmodel = FORCE_GUO) {
   using L = Lat<S>;
   T drho = T(0), j[3] = {T(0), T(0), T(0)};
   sfor<L::Q>([&](auto I) {
@@ -664,7 +693,8 @@ LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr) {
   });
   if constexpr (FORCE) {
     T src[Lat<S>::G];
-    guo_source<S>(src, u, F);
+    if (fmodel == FORCE_HE) he_source<S>(src, feq, u, F, rinv);
+    else guo_source<S>(src, u, F);
     const T wf = T(0.5) * (T(1) + b);  // 1 - omega / 2
     sfor<L::Q>([&](auto I) {
       constexpr int gi = L::gidx(decltype(I)::value);
@@ -677,12 +707,12 @@ LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr) {
 // the collision: g holds df (grid order, missing velocities zero) and receives df*
 // ---------------------------------------------------------------------------------------
 template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
-LBM_HD void collide(T *g, const Relax<T> &R, T grav, const T *F = nullptr) {
+LBM_HD void collide(T *g, const Relax<T> &R, T grav, const T *F = nullptr, int fmodel = FORCE_GUO) {
   if constexpr (SP == SRT) {
-    collide_srt<S, T, FORCE>(g, R, F);
+    collide_srt<S, T, FORCE>(g, R, F, fmodel);
   } else if constexpr (SP != IDENTITY) {
     chimera_forward<S>(g);
-    collide_moments<S, SP, EQ, REG, T, FORCE>(g, R, grav, F);
+    collide_moments<S, SP, EQ, REG, T, FORCE>(g, R, grav, F, fmodel);
     chimera_inverse<S>(g);
   }
 }

@@ -62,6 +62,7 @@ struct SweepArgs {
   const uint2 *tile_table;  // per block: (tx | ty << 16, tz), XCD order applied; or null
   const CT *ffield;  // forced sweep: body force per cell [3][ncells] (natural order), or null
   CT fconst[3];      // forced sweep: constant body force added to ffield
+  int force_model;   // forced sweep: FORCE_GUO or FORCE_HE
   CT grav;
   Relax<CT> R;
 };
@@ -234,7 +235,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       F[2] += a.ffield[2 * nc + cell];
     }
     if constexpr (L::D == 2) F[2] = CT(0);
-    collide<S, SP, EQ, REG, CT, true>(g, a.R, a.grav, F);
+    collide<S, SP, EQ, REG, CT, true>(g, a.R, a.grav, F, a.force_model);
   } else {
     collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
   }

@@ -276,6 +276,7 @@ lbm_status validate(const lbm_params *p) {
   }
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(p->force[d])) return fail(LBM_EINVAL, "force must be finite");
+  if (p->force_model < LBM_FORCE_GUO || p->force_model > LBM_FORCE_HE) return fail(LBM_EINVAL, "force_model out of range");
   const bool forced = p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0;
   if (forced && p->equilibrium != LBM_EQ_MAXWELLIAN)
     return fail(LBM_EUNSUPPORTED, "the body force is implemented with the Maxwellian equilibrium");

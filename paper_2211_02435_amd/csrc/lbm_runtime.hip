@@ -225,6 +225,7 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   a.grav = CT(c->p.gravity);
   a.ffield = static_cast<const CT *>(c->ffield);
   for (int d = 0; d < 3; ++d) a.fconst[d] = CT(c->p.force[d]);
+  a.force_model = c->p.force_model == LBM_FORCE_HE ? FORCE_HE : FORCE_GUO;
   for (int j = 0; j < 6; ++j)
     for (int k = 0; k < 6; ++k) a.R.b2[j][k] = CT(c->R.b2[j][k]);
   for (int j = 0; j < 7; ++j)

@@ -22,6 +22,7 @@ STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 STREAMING = {"pull": 0, "aa": 1, "esoteric": 2}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
+FORCE_MODELS = {"guo": 0, "he": 1}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
 # order of every polynomial of the bases documented in lbm.h (one rate per entry of omegas)
 BASIS_ORDERS = {
@@ -52,7 +53,7 @@ class LbmParams(ctypes.Structure):
                 ("gravity", c_double), ("nx", c_int64), ("ny", c_int64), ("nz", c_int64),
                 ("periodic", c_int * 3), ("storage", c_int), ("streaming", c_int),
                 ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p),
-                ("layout", c_int), ("arithmetic", c_int), ("force", c_double * 3)]
+                ("layout", c_int), ("arithmetic", c_int), ("force", c_double * 3), ("force_model", c_int)]
 
 
 class LbmError(RuntimeError):
@@ -147,7 +148,7 @@ def _dptr(a):
 
 def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", equilibrium="maxwellian",
                 eq_form="default", gravity=0.0, zero_centered=1, layout="auto", arithmetic="deviation",
-                force=(0.0, 0.0, 0.0)):
+                force=(0.0, 0.0, 0.0), force_model="guo"):
     p = LbmParams()
     check(load().lbm_params_default(ctypes.byref(p)))
     p.stencil = STENCILS[stencil]
@@ -167,6 +168,7 @@ def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", e
     p.arithmetic = ARITHMETIC[arithmetic]
     for d in range(3):
         p.force[d] = float(force[d])
+    p.force_model = FORCE_MODELS[force_model]
     return p
 
 
@@ -188,7 +190,7 @@ class Lattice:
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
                  equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto",
-                 zero_centered=True, arithmetic="deviation", force=(0.0, 0.0, 0.0)):
+                 zero_centered=True, arithmetic="deviation", force=(0.0, 0.0, 0.0), force_model="guo"):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
@@ -197,7 +199,7 @@ class Lattice:
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
                         zero_centered=1 if zero_centered else 0, layout=layout, arithmetic=arithmetic,
-                        force=force)
+                        force=force, force_model=force_model)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []

@@ -126,6 +126,10 @@ def test_srt_and_literal_parameter_sets():
     p = _p()
     p.arithmetic = 2
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+    p = _p(force=(1e-4, 0, 0), force_model="he")
+    assert lbm.lbm_validate(p) == 0
+    p.force_model = 2
+    assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
 
 
 def test_params_struct_layout_matches_the_header(tmp_path):

@@ -1,5 +1,5 @@
-"""Body force (sec. 2.1 source term, q^F of eq. MrtUpdateGeneral) with Guo's model on the GPU,
-against the FP64 oracle's forced collision.
+"""Body force (sec. 2.1 source term, q^F of eq. MrtUpdateGeneral) with Guo's and He's models on
+the GPU, against the FP64 oracle's forced collision.
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 4 steps from a non-equilibrium state with a
 random force field plus a constant force; the readers' velocity is Guo's (j + F/2) / rho; the
@@ -35,11 +35,12 @@ def _rates(stencil, space):
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("space", ["raw", "central", "cumulant", "srt"])
 @pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric"])
-def test_forced_sweep_fp64_matches_oracle(stencil, space, streaming):
+@pytest.mark.parametrize("model", ["guo", "he"])
+def test_forced_sweep_fp64_matches_oracle(stencil, space, streaming, model):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     nx, ny, nz = dims
     om = _rates(stencil, space)
-    m = O.Method(stencil, space, om)
+    m = O.Method(stencil, space, om, force_model=model)
     rho, u = W.random_near_equilibrium_fields((nz, ny, nx), seed=5, drho=5e-3, umax=0.04)
     if m.st.d == 2:
         u[2] = 0.0
@@ -50,14 +51,14 @@ def test_forced_sweep_fp64_matches_oracle(stencil, space, streaming):
     if m.st.d == 2:
         field[2] = 0.0
         const[2] = 0.0
-    lat = lbm.Lattice(stencil, space, om, dims, storage="f64", streaming=streaming, force=const)
+    lat = lbm.Lattice(stencil, space, om, dims, storage="f64", streaming=streaming, force=const, force_model=model)
     lat.lbm_set_force_field(field)
     lat.lbm_set_populations(df0)
     lat.lbm_step(4)
     total = field + const[:, None, None, None]
     want = O.step(m, df0, 4, force=total)
     err = np.abs(lat.lbm_get_populations() - want).max()
-    print("forced %s %s %s max|d df| = %.3e" % (stencil, space, streaming, err))
+    print("forced (%s) %s %s %s max|d df| = %.3e" % (model, stencil, space, streaming, err))
     assert err <= 1e-13
     _, ug = lat.lbm_macroscopic()
     _, uo = O.macroscopic(m, want, force=total)
@@ -68,8 +69,8 @@ def test_forced_sweep_fp64_matches_oracle(stencil, space, streaming):
     assert np.abs(lat.lbm_get_populations() - want1).max() <= 1e-13
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
-def test_kolmogorov_flow_on_the_gpu(storage):
+@pytest.mark.parametrize("storage,model", [("f64", "guo"), ("f32", "guo"), ("f64", "he")])
+def test_kolmogorov_flow_on_the_gpu(storage, model):
     """D3Q27 cumulant, z-invariant forcing F_x = F0 sin(k y): steady amplitude F0 / (nu k^2)
     within 1 % at n = 24 (the oracle pins the second-order convergence of this model)."""
     n, nz = 24, 2
@@ -81,12 +82,12 @@ def test_kolmogorov_flow_on_the_gpu(storage):
     F = np.zeros((3, nz, n, n))
     F[0] = F0 * np.sin(k * y)[None, :, None]
     om = O.regularized_rates("D3Q27", omega)
-    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, nz), storage=storage)
+    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, nz), storage=storage, force_model=model)
     lat.lbm_set_force_field(F)
     lat.lbm_init_equilibrium(np.ones((nz, n, n)), np.zeros((3, nz, n, n)))
     lat.lbm_step(1000)
     _, u = lat.lbm_macroscopic()
     amp = 2.0 / n * (u[0, 0, :, 0] * np.sin(k * y)).sum()
     rel = abs(amp / (F0 / (nu * k * k)) - 1.0)
-    print("Kolmogorov %s amplitude rel. error %.3e" % (storage, rel))
+    print("Kolmogorov %s %s amplitude rel. error %.3e" % (storage, model, rel))
     assert rel < 0.01

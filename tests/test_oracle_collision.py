@@ -422,15 +422,16 @@ FORCE_CASES = [("D2Q9", "raw"), ("D2Q9", "cumulant"), ("D3Q19", "central"), ("D3
                ("D3Q27", "central"), ("D3Q27", "cumulant"), ("D3Q27", "srt")]
 
 
+@pytest.mark.parametrize("model", ["guo", "he"])
 @pytest.mark.parametrize("name,space", FORCE_CASES)
-def test_force_adds_exactly_F_of_momentum(name, space):
+def test_force_adds_exactly_F_of_momentum(name, space, model):
     st = O.stencil(name)
     if space == "srt":
         om = np.full(st.q, 1.3)
         om[st.conserved] = 0
     else:
         om = _general_rates(name, 9)
-    m = O.Method(name, space, om)
+    m = O.Method(name, space, om, force_model=model)
     df = _state(m)
     rng = np.random.default_rng(4)
     F = rng.uniform(-1e-3, 1e-3, (df.shape[0], 3))
@@ -463,8 +464,34 @@ def test_uniform_force_accelerates_uniformly():
         np.testing.assert_allclose(uu.reshape(3, -1).T, np.broadcast_to(want, (24, 3)), rtol=0, atol=1e-15)
 
 
+def test_he_source_moments():
+    """He's source carries no mass and exactly F of momentum, and its second moment is
+    u F + F u up to the lattice's O(u^2 F) defect of the equilibrium's third moments (the
+    Hermite expansion of -F . grad_xi f_eq), on every stencil."""
+    for name in ("D2Q9", "D3Q19", "D3Q27"):
+        st = O.stencil(name)
+        m = O.Method(name, "central", O.regularized_rates(name, 1.2), force_model="he")
+        rng = np.random.default_rng(3)
+        rho = 1 + 0.05 * rng.standard_normal(4)
+        u = rng.uniform(-0.05, 0.05, (4, 3))
+        F = rng.uniform(-1e-3, 1e-3, (4, 3))
+        if st.d == 2:
+            u[:, 2] = 0
+            F[:, 2] = 0
+        S = O.he_source(st, u, F, rho, O.equilibrium_populations(m, rho, u))
+        xi = st.xi.astype(float)
+        np.testing.assert_allclose(S.sum(axis=1), 0, atol=1e-18)
+        np.testing.assert_allclose(S @ xi, F, rtol=0, atol=1e-17)
+        for a in range(st.d):
+            for b in range(st.d):
+                got = (S * xi[None, :, a] * xi[None, :, b]).sum(axis=1)
+                tol = 3 * np.abs(u).max() ** 2 * np.abs(F).max()
+                np.testing.assert_allclose(got, u[:, a] * F[:, b] + F[:, a] * u[:, b], rtol=0, atol=tol)
+
+
+@pytest.mark.parametrize("model", ["guo", "he"])
 @pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
-def test_kolmogorov_flow_amplitude_second_order(space):
+def test_kolmogorov_flow_amplitude_second_order(space, model):
     """Steady shear flow under F_x = F0 sin(k y): nu u'' + F = 0 gives u_x = F0 / (nu k^2) sin(k y).
     Guo's model reproduces the amplitude with an error that falls as k^2 (sec. 2.1 source term)."""
     om = O.regularized_rates("D2Q9", 0.8)
@@ -476,7 +503,7 @@ def test_kolmogorov_flow_amplitude_second_order(space):
         y = np.arange(n)
         F = np.zeros((3, 1, n, n))
         F[0] = F0 * np.sin(k * y)[None, :, None]
-        m = O.Method("D2Q9", space, om)
+        m = O.Method("D2Q9", space, om, force_model=model)
         df = O.init_equilibrium(m, np.ones((1, n, n)), np.zeros((3, 1, n, n)))
         df = O.step(m, df, steps, force=F)
         _, u = O.macroscopic(m, df, force=F)
