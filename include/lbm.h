@@ -24,8 +24,10 @@
  *            (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1);
  *            (1,1,1) (-1,-1,-1) (1,1,-1) (-1,-1,1) (1,-1,1) (-1,1,-1) (-1,1,1) (1,-1,-1)
  *     D3Q19: the first 19 velocities of D3Q27.
+ *     D3Q15: the first 7 velocities of D3Q27 and its 8 corners, in D3Q27's order.
  *   Weights (background f0 for the Maxwellian equilibrium, f0 = M^-1 m0 = w, sec. 2.4):
- *     D2Q9 4/9 1/9 1/36; D3Q19 1/3 1/18 1/36; D3Q27 8/27 2/27 1/54 1/216.  c_s^2 = 1/3,
+ *     D2Q9 4/9 1/9 1/36; D3Q19 1/3 1/18 1/36; D3Q27 8/27 2/27 1/54 1/216; D3Q15 2/9 1/9
+ *     (faces) 1/72 (corners).  c_s^2 = 1/3,
  *     rho0 = 1.  For the shallow-water equilibrium f0 = f^eq(h = 1, u = 0).
  *   Polynomial basis, one relaxation rate per entry of `omegas`, in this order
  *   (graded: every polynomial is homogeneous in one order):
@@ -36,6 +38,11 @@
  *            x2y2-2x2z2+y2z2, x2y2+x2z2-2y2z2, x2y2+x2z2+y2z2
  *     D3Q27: the first 16 of D3Q19, xyz, the three fourth-order combinations of D3Q19,
  *            x2yz, xy2z, xyz2, xy2z2, x2yz2, x2y2z, x2y2z2
+ *     D3Q15: 1, x, y, z, xy, xz, yz, x2-y2, x2-z2, x2+y2+z2, xyz, xy2, x2y, x2z, x2y2, where
+ *            xy2 stands for its class on the lattice (xy2 = xz2 = xy2z2 there), x2y for
+ *            (x2y, yz2, x2yz2), x2z for (x2z, y2z, x2y2z) and x2y2 for the corner indicator
+ *            (x2y2 = x2z2 = y2z2 = x2y2z2); D3Q15 runs in raw-moment space and SRT, with the
+ *            second-order polynomial equilibrium (it cannot carry the Maxwellian's moments).
  *     Rates of the conserved polynomials 1, x, y, z are ignored.
  *   Equilibria: LBM_EQ_MAXWELLIAN is the continuous Maxwellian of sec. 2.4; its raw moments
  *     are truncated at second order in u (sec. 4.3), its central moments and cumulants are
@@ -76,7 +83,7 @@ typedef enum {
   LBM_ENONFINITE = -5     /* lbm_diagnostics found NaN or Inf populations                      */
 } lbm_status;
 
-typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2 } lbm_stencil;
+typedef enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1, LBM_D3Q27 = 2, LBM_D3Q15 = 3 } lbm_stencil;
 /* SRT: the single-relaxation-time method in population space (eq. MrtUpdateGeneral with the
  * identity transform and S = omega I, the SRT row of the method table of sec. 4.3); its
  * equilibrium is the second-order polynomial f_eq_i = w_i rho (1 + 3 xi.u + 9/2 (xi.u)^2

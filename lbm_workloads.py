@@ -177,6 +177,8 @@ WORKLOADS = {
                           omega_shear=re_to_omega(0.02, 256, 1600.0), steps=500),
     "d3q27_cumulant_512": dict(stencil="D3Q27", space="cumulant", dims=(512, 512, 512), u0=0.05,
                                omega_shear=re_to_omega(0.05, 512, 1600.0), steps=200),
+    "d3q15_raw_512": dict(stencil="D3Q15", space="raw", dims=(512, 512, 512), u0=0.05,
+                          omega_shear=re_to_omega(0.05, 512, 1600.0), steps=200),
     "batch_d3q27_central": dict(stencil="D3Q27", space="central", nboxes=256, steps=100,
                                 storage="f32"),
     "swe_d2q9_4096": dict(stencil="D2Q9", space="central", equilibrium="swe", dims=(4096, 4096, 1),

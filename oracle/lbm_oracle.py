@@ -9,7 +9,7 @@ Relaxation-Time Lattice Boltzmann Methods", arXiv 2211.02435.
 Every function states the passage it follows and what pins it (the tests in
 tests/test_oracle_*.py check it against something other than itself):
 
-  Stencil / weights          sec. 2.1 (D2Q9/D3Q19/D3Q27, xi_0 = 0)
+  Stencil / weights          sec. 2.1 (D2Q9/D3Q15/D3Q19/D3Q27, xi_0 = 0)
         pin: w == M^-1 m0 (sec. 2.4, background equals the weights), isotropy sums
   moment_matrix              eq. DiscreteRawMomentsDef (sec. 2.3.1)
         pin: closed-form 1-D factorisation, w == M^-1 m0, textbook 2nd-order equilibrium
@@ -79,6 +79,7 @@ _D3Q27 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0
           (1, 1, 1), (-1, -1, -1), (1, 1, -1), (-1, -1, 1),
           (1, -1, 1), (-1, 1, -1), (-1, 1, 1), (1, -1, -1)]
 _D3Q19 = _D3Q27[:19]
+_D3Q15 = _D3Q27[:7] + _D3Q27[19:]  # rest, faces, corners (no edges)
 
 
 def _mono(a, b, c=0):
@@ -121,10 +122,16 @@ _B3_O4 = [
 _B3_HIGH = [_mono(2, 1, 1), _mono(1, 2, 1), _mono(1, 1, 2),
             _mono(1, 2, 2), _mono(2, 1, 2), _mono(2, 2, 1), _mono(2, 2, 2)]
 
+# D3Q15 lacks the edges, so on its velocities every monomial with two or more nonzero
+# exponents equals another one of the same exponent parities (x y^2 = x z^2 = x y^2 z^2,
+# x^2 y^2 = x^2 z^2 = y^2 z^2 = x^2 y^2 z^2, ...); one monomial stands for each such class.
+_B3_15 = _B3_LOW[:10] + [_mono(1, 1, 1), _mono(1, 2, 0), _mono(2, 1, 0), _mono(2, 0, 1), _mono(2, 2, 0)]
+
 _BASES = {
     "D2Q9": _BASIS_2D,
     "D3Q19": _B3_LOW + _B3_O4,
     "D3Q27": _B3_LOW + _B3_XYZ + _B3_O4 + _B3_HIGH,
+    "D3Q15": _B3_15,
 }
 
 BASIS_NAMES = {
@@ -135,13 +142,14 @@ BASIS_NAMES = {
 }
 BASIS_NAMES["D3Q27"] = (BASIS_NAMES["D3Q19"][:16] + ["xyz"] + BASIS_NAMES["D3Q19"][16:]
                         + ["x2yz", "xy2z", "xyz2", "xy2z2", "x2yz2", "x2y2z", "x2y2z2"])
+BASIS_NAMES["D3Q15"] = BASIS_NAMES["D3Q19"][:10] + ["xyz", "xy2", "x2y", "x2z", "x2y2"]
 
 
 class Stencil:
     """Velocity set, lattice weights, monomial set and polynomial basis (sec. 2.1, 2.3)."""
 
     def __init__(self, name):
-        vel = {"D2Q9": _D2Q9, "D3Q19": _D3Q19, "D3Q27": _D3Q27}[name]
+        vel = {"D2Q9": _D2Q9, "D3Q19": _D3Q19, "D3Q27": _D3Q27, "D3Q15": _D3Q15}[name]
         self.name = name
         self.d = 2 if name == "D2Q9" else 3
         self.q = len(vel)
@@ -149,7 +157,8 @@ class Stencil:
         norm2 = (self.xi ** 2).sum(axis=1)
         wtab = {"D2Q9": {0: 4 / 9, 1: 1 / 9, 2: 1 / 36},
                 "D3Q19": {0: 1 / 3, 1: 1 / 18, 2: 1 / 36},
-                "D3Q27": {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216}}[name]
+                "D3Q27": {0: 8 / 27, 1: 2 / 27, 2: 1 / 54, 3: 1 / 216},
+                "D3Q15": {0: 2 / 9, 1: 1 / 9, 3: 1 / 72}}[name]
         self.w = np.array([wtab[int(n)] for n in norm2])
         self.opp = np.array([0] + [i + 1 if i % 2 == 1 else i - 1 for i in range(1, self.q)])
         self.basis = _BASES[name]
@@ -408,6 +417,8 @@ class Method:
         self.gravity = gravity
         assert force_model in ("guo", "he")
         self.force_model = force_model
+        if stencil_name == "D3Q15":
+            assert space in ("raw", "srt") and equilibrium == "maxwellian"
         if space == "srt":
             assert equilibrium == "maxwellian"
             rest = self.omegas[self.st.d + 1:]
@@ -454,6 +465,10 @@ class Method:
             return swe_maxwellian_mono(st, self.space, rho, u, self.gravity)
         if self.space == "srt":
             return srt_equilibrium(st, rho, u)
+        if self.space == "raw" and st.name == "D3Q15":
+            # its monomials coincide in classes, so it cannot carry the Maxwellian's moments:
+            # the equilibrium is the second-order polynomial one, in moments
+            return srt_equilibrium(st, rho, u) @ st.M.T
         if self.space == "raw":
             return raw_maxwellian_truncated(st, rho, u)
         if self.space == "central":

@@ -1,0 +1,4 @@
+// Kernels of stencil d3q15 with f16 population storage.
+#define LBM_TU_STENCIL 3
+#define LBM_TU_STORE 2
+#include "lbm_instantiate.inc"

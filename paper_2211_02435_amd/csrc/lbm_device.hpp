@@ -32,7 +32,7 @@
 
 namespace lbm {
 
-enum StencilId { D2Q9 = 0, D3Q19 = 1, D3Q27 = 2 };
+enum StencilId { D2Q9 = 0, D3Q19 = 1, D3Q27 = 2, D3Q15 = 3 };
 // SRT: single relaxation time in population space (eq. MrtUpdateGeneral with T = identity
 // and S = omega I); IDENTITY: streaming only (no collision)
 enum SpaceId { RAW = 0, CENTRAL = 1, CUMULANT = 2, IDENTITY = 3, SRT = 4 };
@@ -75,12 +75,17 @@ __host__ __device__ constexpr int vel9(int i, int d) {
   return d < 2 ? t[i][d] : 0;
 }
 
+// D3Q15: the rest, the six faces and the eight corners of D3Q27, in D3Q27's order
+__host__ __device__ constexpr int vel15(int i, int d) { return vel27(i < 7 ? i : i + 12, d); }
+
 template <int S>
 struct Lat {
   static constexpr int D = (S == D2Q9) ? 2 : 3;
-  static constexpr int Q = (S == D2Q9) ? 9 : (S == D3Q19 ? 19 : 27);
+  static constexpr int Q = (S == D2Q9) ? 9 : (S == D3Q19 ? 19 : (S == D3Q15 ? 15 : 27));
   static constexpr int G = (D == 2) ? 9 : 27;  // register grid size
-  __host__ __device__ static constexpr int c(int i, int d) { return S == D2Q9 ? vel9(i, d) : vel27(i, d); }
+  __host__ __device__ static constexpr int c(int i, int d) {
+    return S == D2Q9 ? vel9(i, d) : (S == D3Q15 ? vel15(i, d) : vel27(i, d));
+  }
   __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
   // grid index of velocity i
   __host__ __device__ static constexpr int gidx(int i) {
@@ -91,14 +96,31 @@ struct Lat {
     const int n = (c(i, 0) != 0) + (c(i, 1) != 0) + (c(i, 2) != 0);
     if (S == D2Q9) return n == 0 ? 4.0 / 9.0 : (n == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
     if (S == D3Q19) return n == 0 ? 1.0 / 3.0 : (n == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+    if (S == D3Q15) return n == 0 ? 2.0 / 9.0 : (n == 1 ? 1.0 / 9.0 : 1.0 / 72.0);
     return n == 0 ? 8.0 / 27.0 : (n == 1 ? 2.0 / 27.0 : (n == 2 ? 1.0 / 54.0 : 1.0 / 216.0));
   }
-  // is the monomial x^a y^b z^c part of the stencil's moment set?
+  // is the monomial x^a y^b z^c part of the stencil's moment set?  D3Q15 (no edge velocities):
+  // a monomial with two or more nonzero exponents takes on the lattice the values of the
+  // lowest-index one of its exponent-parity class, which represents the class
   __host__ __device__ static constexpr bool has_mono(int a, int b, int cc) {
-    return S == D2Q9 ? (cc == 0) : (S == D3Q19 ? (a == 0 || b == 0 || cc == 0) : true);
+    if (S == D2Q9) return cc == 0;
+    if (S == D3Q19) return a == 0 || b == 0 || cc == 0;
+    if (S == D3Q15) return rep(a + 3 * b + 9 * cc) == a + 3 * b + 9 * cc;
+    return true;
   }
   __host__ __device__ static constexpr bool has_mono_e(int e) {
     return has_mono(e % 3, (e / 3) % 3, e / 9);
+  }
+  // D3Q15: the class representative of monomial e (e itself on the other stencils)
+  __host__ __device__ static constexpr int rep(int e) {
+    if (S != D3Q15) return e;
+    const int a = e % 3, b = (e / 3) % 3, cc = e / 9;
+    if ((a != 0) + (b != 0) + (cc != 0) < 2) return e;  // 1 and the pure powers
+    const int par = (a & 1) + 2 * (b & 1) + 4 * (cc & 1);
+    // parity (x, y, z odd) -> representative: xy 4, xz 10, yz 12, xyz 13, x2y2 8, xy2 7,
+    // x2y 5, x2z 11
+    constexpr int t[8] = {8, 7, 5, 4, 11, 10, 12, 13};
+    return t[par];
   }
   __host__ __device__ static constexpr int ord(int e) { return e % 3 + (e / 3) % 3 + e / 9; }
 };
@@ -487,6 +509,29 @@ LBM_HD void swek_meq_dev(T *m, T dh, T h, const T *u, T grav) {
 }
 
 // ---------------------------------------------------------------------------------------
+// Single relaxation time in population space.  The second-order polynomial equilibrium
+//   f_eq_i = w_i rho (1 + xi.u / cs2 + (xi.u)^2 / (2 cs4) - u.u / (2 cs2))
+// in deviation form about f0 = w:
+//   df_eq_i = w_i (drho + rho (3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u)),
+// relaxed as df* = df_eq + (1 - omega)(df - df_eq); 1 - omega arrives as R.b2[0][0].
+// ---------------------------------------------------------------------------------------
+template <int S, class T>
+LBM_HD void srt_feq_dev(T *feq, T drho, T rho, const T *u) {
+  using L = Lat<S>;
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+    T xu = T(0);
+    if constexpr (cx != 0) xu = cx > 0 ? xu + u[0] : xu - u[0];
+    if constexpr (cy != 0) xu = cy > 0 ? xu + u[1] : xu - u[1];
+    if constexpr (cz != 0) xu = cz > 0 ? xu + u[2] : xu - u[2];
+    const T poly = T(3) * xu + T(4.5) * xu * xu - T(1.5) * uu;
+    feq[L::gidx(i)] = T(L::w(i)) * (drho + rho * poly);
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // Guo's forcing populations (the source term of eq. LbUpdateScheme, sec. 2.1):
 //   S_i = w_i [ (xi_i - u) / cs2 + (xi_i . u) xi_i / cs4 ] . F,  in grid order
 // ---------------------------------------------------------------------------------------
@@ -569,6 +614,13 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   } else if constexpr (EQ == SWEK) {
     static_assert(S == D2Q9, "the shallow-water equilibria are two-dimensional");
     swek_meq_dev(meq, drho, rho, u, grav);
+  } else if constexpr (S == D3Q15) {
+    // D3Q15 cannot carry the Maxwellian's moments: its equilibrium is the second-order
+    // polynomial one, taken to moments by the Chimera (consistent within every class)
+    static_assert(SP == RAW, "D3Q15 is implemented in raw-moment space (and SRT)");
+    sfor<G>([&](auto E) { meq[E] = T(0); });
+    srt_feq_dev<S>(meq, drho, rho, u);
+    chimera_forward<S>(meq);
   } else {
     sfor<G>([&](auto E) {
       constexpr int e = decltype(E)::value;
@@ -636,34 +688,14 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   // dm* = dm_eq + non-equilibrium part; conserved moments exactly (plus F with a force)
   sfor<G>([&](auto E) {
     constexpr int e = decltype(E)::value;
-    if constexpr (!Lat<S>::has_mono_e(e)) m[e] = T(0);
+    if constexpr (!Lat<S>::has_mono_e(e)) m[e] = S == D3Q15 ? m[Lat<S>::rep(e)] : T(0);  // rep(e) < e: final
     else if constexpr (Lat<S>::ord(e) >= 2 || (FORCE && Lat<S>::ord(e) == 1)) m[e] = meq[e] + v[e];
   });
 }
 
 // ---------------------------------------------------------------------------------------
-// Single relaxation time in population space.  The second-order polynomial equilibrium
-//   f_eq_i = w_i rho (1 + xi.u / cs2 + (xi.u)^2 / (2 cs4) - u.u / (2 cs2))
-// in deviation form about f0 = w:
-//   df_eq_i = w_i (drho + rho (3 xi.u + 9/2 (xi.u)^2 - 3/2 u.u)),
-// relaxed as df* = df_eq + (1 - omega)(df - df_eq); 1 - omega arrives as R.b2[0][0].
+// Single relaxation time: see srt_feq_dev above.
 // ---------------------------------------------------------------------------------------
-template <int S, class T>
-LBM_HD void srt_feq_dev(T *feq, T drho, T rho, const T *u) {
-  using L = Lat<S>;
-  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  sfor<L::Q>([&](auto I) {
-    constexpr int i = decltype(I)::value;
-    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
-    T xu = T(0);
-    if constexpr (cx != 0) xu = cx > 0 ? xu + u[0] : xu - u[0];
-    if constexpr (cy != 0) xu = cy > 0 ? xu + u[1] : xu - u[1];
-    if constexpr (cz != 0) xu = cz > 0 ? xu + u[2] : xu - u[2];
-    const T poly = T(3) * xu + T(4.5) * xu * xu - T(1.5) * uu;
-    feq[L::gidx(i)] = T(L::w(i)) * (drho + rho * poly);
-  });
-}
-
 template <int S, class T, bool FORCE = false>
 LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr, int fmodel = FORCE_GUO) {
   using L = Lat<S>;
@@ -727,7 +759,7 @@ LBM_HD void equilibrium_dev(T *g, T drho, const T *u, T grav) {
   } else if constexpr (EQ == SWEK) {
     swek_meq_dev(g, drho, rho, u, grav);
     chimera_inverse<S>(g);
-  } else if constexpr (SP == SRT) {
+  } else if constexpr (SP == SRT || S == D3Q15) {
     sfor<G>([&](auto E) { g[E] = T(0); });
     srt_feq_dev<S>(g, drho, rho, u);
   } else {

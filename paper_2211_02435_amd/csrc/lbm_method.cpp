@@ -19,7 +19,7 @@ lbm_status fail(lbm_status s, const std::string &msg) {
   return s;
 }
 
-int stencil_q(int s) { return s == LBM_D2Q9 ? 9 : (s == LBM_D3Q19 ? 19 : 27); }
+int stencil_q(int s) { return s == LBM_D2Q9 ? 9 : (s == LBM_D3Q19 ? 19 : (s == LBM_D3Q15 ? 15 : 27)); }
 int stencil_d(int s) { return s == LBM_D2Q9 ? 2 : 3; }
 size_t storage_bytes(int st) { return st == LBM_STORE_F64 ? 8 : (st == LBM_STORE_F32 ? 4 : 2); }
 
@@ -93,6 +93,15 @@ static std::vector<Poly> basis_of(int s) {
          {{1, 1, 2, 0}}, {{1, 2, 1, 0}}, {{1, 2, 2, 0}}};
     return B;
   }
+  if (s == LBM_D3Q15) {
+    // graded; the cubic and quartic entries name the representative monomial of their class
+    B = {{{1, 0, 0, 0}}, {{1, 1, 0, 0}}, {{1, 0, 1, 0}}, {{1, 0, 0, 1}},
+         {{1, 1, 1, 0}}, {{1, 1, 0, 1}}, {{1, 0, 1, 1}},
+         {{1, 2, 0, 0}, {-1, 0, 2, 0}}, {{1, 2, 0, 0}, {-1, 0, 0, 2}},
+         {{1, 2, 0, 0}, {1, 0, 2, 0}, {1, 0, 0, 2}},
+         {{1, 1, 1, 1}}, {{1, 1, 2, 0}}, {{1, 2, 1, 0}}, {{1, 2, 0, 1}}, {{1, 2, 2, 0}}};
+    return B;
+  }
   B = {{{1, 0, 0, 0}}, {{1, 1, 0, 0}}, {{1, 0, 1, 0}}, {{1, 0, 0, 1}},
        {{1, 1, 1, 0}}, {{1, 1, 0, 1}}, {{1, 0, 1, 1}},
        {{1, 2, 0, 0}, {-1, 0, 2, 0}}, {{1, 2, 0, 0}, {-1, 0, 0, 2}},
@@ -120,6 +129,12 @@ static bool mono_present(int s, int e) {
   const int a = e % 3, b = (e / 3) % 3, c = e / 9;
   if (s == LBM_D2Q9) return c == 0;
   if (s == LBM_D3Q19) return a == 0 || b == 0 || c == 0;
+  if (s == LBM_D3Q15) {
+    // 1 and the pure powers, and one representative per exponent-parity class of the mixed
+    // monomials: xy, xz, yz, xyz, x2y2, xy2, x2y, x2z
+    if ((a != 0) + (b != 0) + (c != 0) < 2) return true;
+    return e == 4 || e == 10 || e == 12 || e == 13 || e == 8 || e == 7 || e == 5 || e == 11;
+  }
   return true;
 }
 
@@ -235,7 +250,7 @@ lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
 
 lbm_status validate(const lbm_params *p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
-  if (p->stencil < LBM_D2Q9 || p->stencil > LBM_D3Q27) return fail(LBM_EINVAL, "stencil out of range");
+  if (p->stencil < LBM_D2Q9 || p->stencil > LBM_D3Q15) return fail(LBM_EINVAL, "stencil out of range");
   if (p->space < LBM_SPACE_RAW || p->space > LBM_SPACE_SRT) return fail(LBM_EINVAL, "space out of range");
   if (p->arithmetic < LBM_ARITH_DEVIATION || p->arithmetic > LBM_ARITH_LITERAL)
     return fail(LBM_EINVAL, "arithmetic out of range");
@@ -267,6 +282,14 @@ lbm_status validate(const lbm_params *p) {
   if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
     return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");
   if (p->stencil == LBM_D2Q9 && p->nz != 1) return fail(LBM_EUNSUPPORTED, "D2Q9 requires nz == 1");
+  if (p->stencil == LBM_D3Q15) {
+    if (p->space != LBM_SPACE_RAW && p->space != LBM_SPACE_SRT)
+      return fail(LBM_EUNSUPPORTED, "D3Q15 is implemented in raw-moment space and SRT");
+    if (p->equilibrium != LBM_EQ_MAXWELLIAN)
+      return fail(LBM_EUNSUPPORTED, "D3Q15 takes the polynomial Maxwellian equilibrium");
+    if (p->arithmetic != LBM_ARITH_DEVIATION)
+      return fail(LBM_EUNSUPPORTED, "D3Q15 runs with the deviation arithmetic");
+  }
   if (p->space == LBM_SPACE_SRT) {
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
       return fail(LBM_EUNSUPPORTED, "SRT is implemented with the Maxwellian (polynomial) equilibrium");

@@ -39,6 +39,9 @@ namespace lbm {
     case 6: return KTable<D3Q27, F64>::FN(__VA_ARGS__);                           \
     case 7: return KTable<D3Q27, F32>::FN(__VA_ARGS__);                           \
     case 8: return KTable<D3Q27, F16>::FN(__VA_ARGS__);                           \
+    case 9: return KTable<D3Q15, F64>::FN(__VA_ARGS__);                           \
+    case 10: return KTable<D3Q15, F32>::FN(__VA_ARGS__);                          \
+    case 11: return KTable<D3Q15, F16>::FN(__VA_ARGS__);                          \
   }                                                                               \
   return nullptr;
 
@@ -1176,6 +1179,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   *out = nullptr;
   if (!common || !dims || !omegas || nboxes < 1) return fail(LBM_EINVAL, "bad batch arguments");
   if (common->stencil == LBM_D2Q9) return fail(LBM_EUNSUPPORTED, "the batched ensemble is three-dimensional");
+  if (common->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "the batched ensemble runs D3Q19 and D3Q27");
   if (common->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the pull pattern");
   if (common->equilibrium != LBM_EQ_MAXWELLIAN) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the Maxwellian");
   if (!common->zero_centered) return fail(LBM_EUNSUPPORTED, "the batched ensemble stores zero-centred populations");

@@ -14,7 +14,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpaper_lbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EUNSUPPORTED, LBM_ENOMEM, LBM_EDEVICE, LBM_ENONFINITE = 0, -1, -2, -3, -4, -5
-STENCILS = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2}
+STENCILS = {"D2Q9": 0, "D3Q19": 1, "D3Q27": 2, "D3Q15": 3}
 SPACES = {"raw": 0, "central": 1, "cumulant": 2, "srt": 3}
 EQUILIBRIA = {"maxwellian": 0, "swe": 1, "swe_maxwellian": 2}
 EQ_FORMS = {"default": 0, "absolute": 1, "delta": 2}
@@ -23,16 +23,17 @@ STREAMING = {"pull": 0, "aa": 1, "esoteric": 2}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
 FORCE_MODELS = {"guo": 0, "he": 1}
-Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27}
+Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27, "D3Q15": 15}
 # order of every polynomial of the bases documented in lbm.h (one rate per entry of omegas)
 BASIS_ORDERS = {
     "D2Q9": [0, 1, 1, 2, 2, 2, 3, 3, 4],
     "D3Q19": [0, 1, 1, 1] + [2] * 6 + [3] * 6 + [4] * 3,
     "D3Q27": [0, 1, 1, 1] + [2] * 6 + [3] * 6 + [3] + [4] * 3 + [4] * 3 + [5] * 3 + [6],
+    "D3Q15": [0, 1, 1, 1] + [2] * 6 + [3] * 4 + [4],
 }
 # positions of the shear polynomials (xy, xz, yz, x2-y2, x2-z2) and of the trace x2+y2(+z2)
-SHEAR = {"D2Q9": [3, 4], "D3Q19": [4, 5, 6, 7, 8], "D3Q27": [4, 5, 6, 7, 8]}
-TRACE = {"D2Q9": 5, "D3Q19": 9, "D3Q27": 9}
+SHEAR = {"D2Q9": [3, 4], "D3Q19": [4, 5, 6, 7, 8], "D3Q27": [4, 5, 6, 7, 8], "D3Q15": [4, 5, 6, 7, 8]}
+TRACE = {"D2Q9": 5, "D3Q19": 9, "D3Q27": 9, "D3Q15": 9}
 
 
 def regularized_rates(stencil, omega_shear, omega_bulk=1.0):

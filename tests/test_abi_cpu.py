@@ -132,6 +132,29 @@ def test_srt_and_literal_parameter_sets():
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
 
 
+def test_d3q15_parameter_sets():
+    """D3Q15 runs in raw-moment space and as SRT, with the polynomial equilibrium, on every
+    storage and streaming pattern; the other spaces, the shallow-water equilibria and the
+    literal arithmetic are rejected."""
+    om = O.regularized_rates("D3Q15", 1.6)
+    srt = np.r_[np.zeros(4), np.full(11, 1.6)]
+    for store in ("f64", "f32", "f16"):
+        for stream in ("pull", "aa", "esoteric"):
+            for sp, w in (("raw", om), ("srt", srt)):
+                p = _p(stencil="D3Q15", space=sp, omegas=w, storage=store, streaming=stream)
+                assert lbm.lbm_validate(p) == 0, (sp, store, stream, lbm.last_error())
+    assert lbm.lbm_validate(_p(stencil="D3Q15", space="raw", omegas=om, force=(1e-5, 0, 0))) == 0
+    assert lbm.lbm_validate(_p(stencil="D3Q15", space="raw", omegas=om, zero_centered=0)) == 0
+    for kw in (dict(space="central"), dict(space="cumulant"),
+               dict(space="raw", arithmetic="literal"),
+               dict(space="raw", equilibrium="swe", gravity=0.1)):
+        assert lbm.lbm_validate(_p(stencil="D3Q15", omegas=om, **kw)) == lbm.LBM_EUNSUPPORTED, kw
+        assert lbm.last_error() != ""
+    assert lbm.lbm_validate(_p(stencil="D3Q15", space="raw", omegas=np.ones(27))) == lbm.LBM_EINVAL
+    assert lbm.lbm_required_bytes(_p(stencil="D3Q15", space="raw", omegas=om, dims=(10, 6, 4),
+                                     storage="f32")) % (2 * 15 * 256) == 0
+
+
 def test_params_struct_layout_matches_the_header(tmp_path):
     """The ctypes mirror of lbm_params has the C compiler's size and field offsets."""
     fields = [f[0] for f in lbm.LbmParams._fields_]

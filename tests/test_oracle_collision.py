@@ -14,7 +14,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
 CASES = [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
          ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
-         ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")]
+         ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant"), ("D3Q15", "raw")]
 
 
 def _general_rates(name, seed):
@@ -120,7 +120,7 @@ def _srt(name, omega):
     return O.Method(name, "srt", om)
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q15", "D3Q19", "D3Q27"])
 def test_srt_equilibrium_moments(name):
     """The polynomial equilibrium carries the Maxwellian's moments up to second order:
     sum f = rho, sum f xi = rho u, sum f xi_a xi_b = rho (cs2 delta_ab + u_a u_b)."""
@@ -143,7 +143,7 @@ def test_srt_equilibrium_moments(name):
                 assert abs(m2 - want) < 1e-15
 
 
-@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q15", "D3Q19", "D3Q27"])
 def test_srt_forms_agree_conserve_and_relax(name):
     m = _srt(name, 1.43)
     df = _state(m)
@@ -188,6 +188,58 @@ def test_srt_differs_from_raw_moment_bgk_on_d3q19():
     m220 = sum(feq[i] * st.xi[i, 0] ** 2 * st.xi[i, 1] ** 2 for i in range(st.q))
     want = 1 / 9 + (0.03 ** 2 + 0.02 ** 2) / 3 - 0.05 ** 2 / 6
     assert abs(m220 - want) < 1e-16
+
+
+def test_d3q15_monomial_classes_by_brute_force():
+    """D3Q15 (rest, faces, corners): every monomial x^a y^b z^c (a, b, c <= 2) with two or more
+    nonzero exponents takes on each velocity the value of the basis monomial with the same
+    exponent parities, and the monomials of the basis are the only independent ones."""
+    st = O.stencil("D3Q15")
+    xi = st.xi.astype(float)
+
+    def row(e):
+        return np.array([xi[i, 0] ** e[0] * xi[i, 1] ** e[1] * xi[i, 2] ** e[2] for i in range(st.q)])
+
+    reps = [e for e in st.exps if sum(1 for k in e if k) >= 2]
+    assert len(reps) == 8
+    for a in range(3):
+        for b in range(3):
+            for c in range(3):
+                e = (a, b, c)
+                if sum(1 for k in e if k) < 2:
+                    continue
+                par = tuple(k % 2 for k in e)
+                same = [r for r in reps if tuple(k % 2 for k in r) == par]
+                assert len(same) == 1, e
+                np.testing.assert_array_equal(row(e), row(same[0]))
+    assert np.linalg.matrix_rank(st.M) == 15
+
+
+def test_d3q15_polynomial_equilibrium_fourth_moment():
+    """On D3Q15 only the corners carry x^2 y^2; summing the second-order polynomial equilibrium
+    over them by hand gives m_xxyy = rho (1/9 + |u|^2 / 3), the same for xx zz and yy zz."""
+    st = O.stencil("D3Q15")
+    rho = np.array([1.02])
+    u = np.array([[0.03, -0.02, 0.05]])
+    feq = O.srt_equilibrium(st, rho, u)[0]
+    want = 1.02 * (1 / 9 + (0.03 ** 2 + 0.02 ** 2 + 0.05 ** 2) / 3)
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        mom = sum(feq[i] * st.xi[i, a] ** 2 * st.xi[i, b] ** 2 for i in range(st.q))
+        assert abs(mom - want) < 1e-16
+
+
+def test_d3q15_raw_moment_bgk_equals_srt():
+    """The raw-moment collision on D3Q15 with one rate on every non-conserved polynomial
+    equals the population-space BGK collision with that rate."""
+    st = O.stencil("D3Q15")
+    om = np.full(st.q, 1.31)
+    om[st.conserved] = 0
+    raw = O.Method("D3Q15", "raw", om)
+    m = _srt("D3Q15", 1.31)
+    df = _state(m)
+    for form in ("delta", "zc_absolute"):
+        np.testing.assert_allclose(O.collide_cells(raw, df, form), O.collide_cells(m, df, "delta"),
+                                   rtol=0, atol=2e-15)
 
 
 def test_worked_propagation_example():
@@ -415,6 +467,20 @@ def test_taylor_green_energy_decay_d3q27_cumulant():
     assert abs(rate / (4 * nu * k * k) - 1) < 1e-2
     d = O.diagnostics(m, df)
     assert abs(d[0] - d0[0]) < 1e-11 and np.abs(d[1:4] - d0[1:4]).max() < 1e-12
+
+
+def test_taylor_green_decay_d3q15_raw():
+    """z-invariant Taylor-Green vortex on D3Q15 with regularized raw-moment rates: the decay
+    rate of the velocity amplitude is 2 nu k^2 within 1 %."""
+    omega = 1.1
+    m = O.Method("D3Q15", "raw", O.regularized_rates("D3Q15", omega))
+    n = 32
+    amps = _tgv_amplitude(m, n, 1, 1e-3, 160, 20)
+    nu = O.omega_to_viscosity(omega)
+    k = 2 * math.pi / n
+    t = np.arange(0, 161, 20)
+    rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
+    assert abs(rate / (2 * nu * k * k) - 1) < 1e-2
 
 
 # ---------------------------------------------------------------- body force (Guo's model)

@@ -16,7 +16,7 @@ import pytest
 import oracle as O
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
-STENCILS = ["D2Q9", "D3Q19", "D3Q27"]
+STENCILS = ["D2Q9", "D3Q15", "D3Q19", "D3Q27"]
 
 
 @pytest.mark.parametrize("name", STENCILS)
@@ -28,6 +28,8 @@ def test_stencil_structure(name):
     np.testing.assert_array_equal(st.xi[st.opp], -st.xi)
     if name == "D3Q19":
         assert (np.abs(st.xi).sum(axis=1) <= 2).all()
+    if name == "D3Q15":  # rest, the six faces and the eight corners
+        assert sorted(np.abs(st.xi).sum(axis=1).tolist()) == [0] + [1] * 6 + [3] * 8
 
 
 @pytest.mark.parametrize("name", STENCILS)
