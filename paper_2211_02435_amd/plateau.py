@@ -20,10 +20,13 @@ This module runs that experiment on the GPU through the library:
     with every rate equal to 1 the relaxation sets each non-conserved moment to its
     equilibrium value whatever the basis;
   * the vortex does not vary along z and every cell is updated by the same arithmetic, so all
-    z-planes stay bit-identical and an L x L x nz box gives the E/E0 of the L^3 box for any nz.
+    z-planes stay bit-identical and an L x L x nz box gives the E/E0 of the L^3 box for any nz;
+  * with FP16 storage (FP32 arithmetic) the literal forms do not exist, so the comparison is
+    of the storage format alone: absolute against zero-centred populations, both collided by
+    the deviation arithmetic.
 
   python -m paper_2211_02435_amd.plateau [--n 256] [--nz 1] [--steps 200000]
-      [--storage f64|f32] [--every 20000] [--json out.json]
+      [--storage f64|f32|f16] [--every 20000] [--json out.json]
 """
 import argparse
 import json
@@ -43,6 +46,17 @@ COLUMNS = [
     ("zero-centred, delta f_eq", dict(zero_centered=True, eq_form="default", arithmetic="deviation")),
     ("zero-centred, delta f_eq subtracted", dict(zero_centered=True, eq_form="delta", arithmetic="literal")),
 ]
+
+
+# FP16 storage: the storage format alone (absolute or zero-centred), deviation arithmetic
+COLUMNS_F16 = [
+    ("absolute storage", dict(zero_centered=False, eq_form="default", arithmetic="deviation")),
+    ("zero-centred, delta f_eq", dict(zero_centered=True, eq_form="default", arithmetic="deviation")),
+]
+
+
+def columns(storage):
+    return COLUMNS_F16 if storage == "f16" else COLUMNS
 
 
 def admissible(space, column):
@@ -83,7 +97,7 @@ def table(n=256, nz=1, steps=200000, storage="f64", every=20000, log=None):
     rows = []
     for name, space in METHODS:
         row = {"method": name, "space": space}
-        for cname, col in COLUMNS:
+        for cname, col in columns(storage):
             if not admissible(space, col):
                 row[cname] = None
                 continue
@@ -105,17 +119,18 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--nz", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200000)
-    ap.add_argument("--storage", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--storage", default="f64", choices=["f64", "f32", "f16"])
     ap.add_argument("--every", type=int, default=20000)
     ap.add_argument("--json", default=None)
     a = ap.parse_args(argv)
     rows = table(a.n, a.nz, a.steps, a.storage, a.every, log=lambda s: print(s, flush=True))
     print("\nE/E0 after %d steps, D3Q27, L = %d, %s storage (analytic %.2e)"
           % (a.steps, a.n, a.storage, rows[0]["analytic"]))
-    print("%-12s" % "method" + "".join("%26s" % c[0][:25] for c in COLUMNS))
+    cols = columns(a.storage)
+    print("%-12s" % "method" + "".join("%26s" % c[0][:25] for c in cols))
     for r in rows:
         print("%-12s" % r["method"] + "".join("%26s" % ("-" if r[c[0]] is None else "%.1e" % r[c[0]])
-                                            for c in COLUMNS))
+                                            for c in cols))
     if a.json:
         with open(a.json, "w") as f:
             json.dump({"n": a.n, "nz": a.nz, "steps": a.steps, "storage": a.storage, "rows": rows}, f, indent=1)

@@ -82,3 +82,18 @@ def test_plateau_ordering_of_the_storage_and_equilibrium_forms(space):
         assert c < a / 100
     # the best zero-centred plateau reaches the level of eps^2 (E is quadratic in u)
     assert min(v, c) < 100 * EPS * EPS
+
+
+@pytest.mark.parametrize("space", ["srt", "raw", "central", "cumulant"])
+def test_fp16_storage_plateau(space):
+    """FP16 storage, FP32 arithmetic (deviation form), the paper's configuration: absolute
+    populations carry the background w_i at FP16 resolution (ulp(8/27) = 2^-12), so the velocity
+    is resolved to about 1e-4 and E/E0 stalls near (1e-4 / u0)^2; zero-centred populations keep
+    FP16's relative resolution as they decay, so their plateau lies orders of magnitude lower."""
+    cols = dict(PL.COLUMNS_F16)
+    a = PL.run(space, cols["absolute storage"], n=N, nz=1, steps=STEPS, storage="f16", every=STEPS)["ratio"]
+    z = PL.run(space, cols["zero-centred, delta f_eq"], n=N, nz=1, steps=STEPS, storage="f16",
+               every=STEPS)["ratio"]
+    print("F16 %-9s absolute %.2e zero-centred %.2e" % (space, a, z), flush=True)
+    assert a > 1e-9
+    assert z < a / 100
