@@ -86,14 +86,21 @@ def test_plateau_ordering_of_the_storage_and_equilibrium_forms(space):
 
 @pytest.mark.parametrize("space", ["srt", "raw", "central", "cumulant"])
 def test_fp16_storage_plateau(space):
-    """FP16 storage, FP32 arithmetic (deviation form), the paper's configuration: absolute
-    populations carry the background w_i at FP16 resolution (ulp(8/27) = 2^-12), so the velocity
-    is resolved to about 1e-4 and E/E0 stalls near (1e-4 / u0)^2; zero-centred populations keep
-    FP16's relative resolution as they decay, so their plateau lies orders of magnitude lower."""
+    """FP16 storage, FP32 arithmetic (deviation form), the paper's configuration.  Absolute
+    populations hold w_i + df_i at the resolution of w_i (ulp(8/27) = 2^-12, ulp(2/27) = 2^-14):
+    each step's viscous decrement of df, about 2 nu k^2 = 2e-4 of it, falls below half an ulp
+    once df is small against w_i, so the decay lags the analytic one, and when df itself drops
+    under half an ulp every population rounds back to w_i and the vortex is erased (E = 0).
+    Zero-centred populations keep FP16's relative resolution: the decay follows the analytic
+    curve at 20 000 steps and stalls only at E/E0 ~ 1e-6."""
     cols = dict(PL.COLUMNS_F16)
-    a = PL.run(space, cols["absolute storage"], n=N, nz=1, steps=STEPS, storage="f16", every=STEPS)["ratio"]
-    z = PL.run(space, cols["zero-centred, delta f_eq"], n=N, nz=1, steps=STEPS, storage="f16",
-               every=STEPS)["ratio"]
-    print("F16 %-9s absolute %.2e zero-centred %.2e" % (space, a, z), flush=True)
-    assert a > 1e-9
-    assert z < a / 100
+    a = PL.run(space, cols["absolute storage"], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
+    z = PL.run(space, cols["zero-centred, delta f_eq"], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
+    analytic20 = math.exp(-4.0 / 6.0 * (2.0 * math.pi / N) ** 2 * 20000)
+    a20, z20 = dict(a["trace"])[20000], dict(z["trace"])[20000]
+    print("F16 %-9s at 20000: analytic %.2e absolute %.2e zero-centred %.2e; final absolute %.2e "
+          "zero-centred %.2e" % (space, analytic20, a20, z20, a["ratio"], z["ratio"]), flush=True)
+    assert abs(z20 / analytic20 - 1) < 0.5
+    assert a20 > 10 * analytic20
+    assert 0 < z["ratio"] < 1e-5
+    assert a["ratio"] == 0.0 or a["ratio"] > 5 * z["ratio"]
