@@ -109,8 +109,17 @@ typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_sto
 /* ESOTERIC_PULL: one array, in place (sec. 4.4): every step a cell touches its own slots and
  * the neighbours x + xi of one direction of each opposite pair (the odd indices); population i
  * of an odd direction (and the rest) is kept at the cell, that of an even direction at
- * x - xi, in slot opp(i) after an even number of steps and in slot i after an odd number. */
-typedef enum { LBM_STREAM_PULL = 0, LBM_STREAM_AA = 1, LBM_STREAM_ESOTERIC_PULL = 2 } lbm_streaming;
+ * x - xi, in slot opp(i) after an even number of steps and in slot i after an odd number.
+ * ESOTERIC_TWIST: one array, in place (sec. 4.4): every step a cell touches the nodes
+ * x + {0,1}^3 only; population i is kept at x + (-xi)^+ (componentwise positive part), in
+ * slot i after an even number of steps and in slot opp(i) after an odd number.  Readers,
+ * writers and lbm_set_time translate every layout to and from the canonical df(t). */
+typedef enum {
+  LBM_STREAM_PULL = 0,
+  LBM_STREAM_AA = 1,
+  LBM_STREAM_ESOTERIC_PULL = 2,
+  LBM_STREAM_ESOTERIC_TWIST = 3
+} lbm_streaming;
 
 /* How the collision's arithmetic is organised.  DEVIATION: every intermediate is a deviation
  * from the background (raw, central and cumulant moments of df, the equilibrium deviation

@@ -1,8 +1,8 @@
 // HIP kernels of the lattice Boltzmann library (gfx950).
 //
 // sweep_kernel   fused stream + collide over every cell (eq. LbUpdateScheme, sec. 2.1, with
-//                the collision of sec. 2.2) for the pull, AA and Esoteric-Pull patterns
-//                (sec. 4.4)
+//                the collision of sec. 2.2) for the pull, AA, Esoteric-Pull and
+//                Esoteric-Twist patterns (sec. 4.4)
 // init_kernel    zero-centred equilibrium initialisation in FP64 (sec. 2.4)
 // export_kernel / import_kernel   canonical df(t) <-> storage layout
 // macro_kernel   density and velocity of df(t) (eq. DensityAndVelocityFromDeviation)
@@ -24,6 +24,11 @@
 //                  even i at x - xi; on even steps population i is found in slot opp(i), on
 //                  odd steps in slot i.  After the collision odd directions are written to
 //                  x + xi, the others stay, the slot index flipping with the parity.
+//   Esoteric Twist: every step touches the nodes x + {0, 1}^3 only.  Population i lives at
+//                  x + (-xi)^+ (componentwise positive part), in slot i after an even number
+//                  of steps and in slot opp(i) after an odd number; after the collision it is
+//                  written to x + (xi)^+ = the home node of opp(i), in the other slot.  The
+//                  two step kinds differ only in the slot naming.
 #pragma once
 
 #include "lbm_device.hpp"
@@ -212,6 +217,10 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
     } else if constexpr (PAT == AA_ODD) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+    } else if constexpr (PAT == TW_EVEN || PAT == TW_ODD) {
+      // Esoteric Twist: population i sits at x + (-xi)^+, slot i on even steps, opp(i) on odd
+      constexpr int slot = PAT == TW_EVEN ? i : L::opp(i);
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(slot) * a.L.ps) + nb.zpart(cz < 0, 1), nb.lane(cx < 0, cy < 0, 1)));
     } else {
       // Esoteric Pull: odd directions (and the rest) sit at the own node, their opposites at
       // x - xi; even steps find every population in the opposite slot, odd steps in its own
@@ -251,6 +260,10 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       stp(a.dst, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else if constexpr (PAT == AA_ODD) {
       stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
+    } else if constexpr (PAT == TW_EVEN || PAT == TW_ODD) {
+      // to x + (xi)^+, the home node of opp(i), in the other slot than the one read
+      constexpr int slot = PAT == TW_EVEN ? L::opp(i) : i;
+      stp(a.dst, (uint64_t(slot) * a.L.ps) + nb.zpart(cz > 0, 1), nb.lane(cx > 0, cy > 0, 1), v);
     } else {
       // odd directions go to x + xi, the others stay; the even step keeps the slot index,
       // the odd step writes the opposite slot (the same locations the loads read)
@@ -394,6 +407,10 @@ __device__ __forceinline__ void canon_addr(const Nbr<Lat<S>::D> &nb, const Strid
   } else if constexpr (GM == G_AA_ODD) {
     uni = uint64_t(Lat<S>::opp(i)) * L.ps + nb.zpart(cz, -1);
     lane = nb.lane(cx, cy, -1);
+  } else if constexpr (GM == G_TW_EVEN || GM == G_TW_ODD) {
+    // Esoteric Twist: slot i (even times) or opp(i) (odd times) at x + (-xi)^+
+    uni = uint64_t(GM == G_TW_EVEN ? i : Lat<S>::opp(i)) * L.ps + nb.zpart(cz < 0, 1);
+    lane = nb.lane(cx < 0, cy < 0, 1);
   } else {
     // Esoteric Pull: slot opp(i) (even times) or i (odd times); odd i at the own node,
     // even i > 0 at x - xi
@@ -427,7 +444,7 @@ __device__ __forceinline__ void gather_canon(const FieldArgs &a, const CellPos &
 }
 
 // df(0) = f_eq(rho, u) - f0, written in layout GM (G_SHIFTED for pull, G_NATURAL for AA,
-// G_ESO_EVEN for Esoteric Pull)
+// G_ESO_EVEN for Esoteric Pull, G_TW_EVEN for Esoteric Twist)
 template <int S, int SP, int EQ, int GM, class ST>
 __global__ void __launch_bounds__(256) init_kernel(FieldArgs a) {
   using L = Lat<S>;

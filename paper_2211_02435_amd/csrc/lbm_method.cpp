@@ -258,7 +258,7 @@ lbm_status validate(const lbm_params *p) {
     return fail(LBM_EINVAL, "equilibrium out of range");
   if (p->eq_form < LBM_EQFORM_DEFAULT || p->eq_form > LBM_EQFORM_DELTA) return fail(LBM_EINVAL, "eq_form out of range");
   if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return fail(LBM_EINVAL, "storage out of range");
-  if (p->streaming < LBM_STREAM_PULL || p->streaming > LBM_STREAM_ESOTERIC_PULL)
+  if (p->streaming < LBM_STREAM_PULL || p->streaming > LBM_STREAM_ESOTERIC_TWIST)
     return fail(LBM_EINVAL, "streaming out of range");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "dims must be >= 1");
   const int q = stencil_q(p->stencil);

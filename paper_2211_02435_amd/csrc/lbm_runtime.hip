@@ -279,21 +279,38 @@ static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src
   }
 }
 
+// sweep kernel pattern of the step that starts at time t, and the layout of df(t)
+static int step_pattern(const lbm_ctx *c, int64_t t) {
+  const bool even = t % 2 == 0;
+  switch (c->pattern) {
+    case LBM_STREAM_AA: return even ? AA_EVEN : AA_ODD;
+    case LBM_STREAM_ESOTERIC_PULL: return even ? ESO_EVEN : ESO_ODD;
+    case LBM_STREAM_ESOTERIC_TWIST: return even ? TW_EVEN : TW_ODD;
+  }
+  return PULL;
+}
+static int gather_mode_at(const lbm_ctx *c, int64_t t) {
+  const bool even = t % 2 == 0;
+  switch (c->pattern) {
+    case LBM_STREAM_AA: return even ? G_NATURAL : G_AA_ODD;
+    case LBM_STREAM_ESOTERIC_PULL: return even ? G_ESO_EVEN : G_ESO_ODD;
+    case LBM_STREAM_ESOTERIC_TWIST: return even ? G_TW_EVEN : G_TW_ODD;
+  }
+  return G_SHIFTED;
+}
+
 // one step with the context's current state; advances cur / t
 static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
   const int sp = sp_override >= 0 ? sp_override : c->space;
   const int reg = sp_override >= 0 ? 0 : (c->reg ? 1 : 0);
   const int eq = sp_override >= 0 ? MAXWELL : c->eq;
-  int pat;
+  const int pat = step_pattern(c, c->t);
   const void *src;
   void *dst;
   if (c->pattern == LBM_STREAM_PULL) {
-    pat = PULL;
     src = c->buf[c->cur];
     dst = c->buf[c->cur ^ 1];
   } else {
-    if (c->pattern == LBM_STREAM_AA) pat = (c->t % 2 == 0) ? AA_EVEN : AA_ODD;
-    else pat = (c->t % 2 == 0) ? ESO_EVEN : ESO_ODD;
     src = c->buf[0];
     dst = c->buf[0];
   }
@@ -320,11 +337,7 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
   return LBM_OK;
 }
 
-static int state_gather_mode(const lbm_ctx *c) {
-  if (c->pattern == LBM_STREAM_PULL) return G_SHIFTED;
-  if (c->pattern == LBM_STREAM_AA) return (c->t % 2 == 0) ? G_NATURAL : G_AA_ODD;
-  return (c->t % 2 == 0) ? G_ESO_EVEN : G_ESO_ODD;
-}
+static int state_gather_mode(const lbm_ctx *c) { return gather_mode_at(c, c->t); }
 static void *state_buffer(const lbm_ctx *c) { return c->pattern == LBM_STREAM_PULL ? c->buf[c->cur] : c->buf[0]; }
 
 static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
@@ -506,7 +519,7 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const 
   }
   c->t = 0;
   c->cur = 0;
-  const int gm = c->pattern == LBM_STREAM_PULL ? G_SHIFTED : (c->pattern == LBM_STREAM_AA ? G_NATURAL : G_ESO_EVEN);
+  const int gm = gather_mode_at(c, 0);
   const int sp_init = c->eq == SWE ? CENTRAL : c->space;
   FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
   a.rho_in = drho;
@@ -740,8 +753,7 @@ extern "C" lbm_status lbm_set_time(lbm_ctx *c, int64_t t) {
     lbm_status s = ensure_staging(c, 2 * n);
     if (s != LBM_OK) return s;
     const int gm_old = state_gather_mode(c);
-    const int gm_new = c->pattern == LBM_STREAM_AA ? ((t % 2 == 0) ? G_NATURAL : G_AA_ODD)
-                                                    : ((t % 2 == 0) ? G_ESO_EVEN : G_ESO_ODD);
+    const int gm_new = gather_mode_at(c, t);
     for (int i0 = 0; i0 < c->q; i0 = (i0 == 0 ? 1 : i0 + 2)) {
       FieldArgs a = field_args(c, c->buf[0], FBX, FBY);
       a.pop = c->staging;

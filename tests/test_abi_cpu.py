@@ -65,6 +65,7 @@ def test_valid_parameter_sets():
     assert b32 % (2 * 27 * 256) == 0 and b32 >= 2 * 27 * 256 * 4
     b16 = lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f16", streaming="aa"))
     assert lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f16", streaming="esoteric")) == b16
+    assert lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f16", streaming="twist")) == b16
     assert b16 % (27 * 256) == 0 and b16 >= 27 * 240 * 2
 
 
@@ -89,6 +90,7 @@ def test_valid_parameter_sets():
     (dict(space="raw", arithmetic="literal", storage="f16"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="aa"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="esoteric"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="raw", arithmetic="literal", streaming="twist"), lbm.LBM_EUNSUPPORTED),
     (dict(space="cumulant", arithmetic="literal", eq_form="delta"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_invalid_parameter_sets(kw, code):
@@ -103,6 +105,9 @@ def test_invalid_parameter_sets(kw, code):
 def test_layout_enum_checked_and_large_boxes_accepted():
     p = _p()
     p.layout = 7
+    assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+    p = _p()
+    p.streaming = 4
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
     # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
     assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
@@ -139,7 +144,7 @@ def test_d3q15_parameter_sets():
     om = O.regularized_rates("D3Q15", 1.6)
     srt = np.r_[np.zeros(4), np.full(11, 1.6)]
     for store in ("f64", "f32", "f16"):
-        for stream in ("pull", "aa", "esoteric"):
+        for stream in ("pull", "aa", "esoteric", "twist"):
             for sp, w in (("raw", om), ("srt", srt)):
                 p = _p(stencil="D3Q15", space=sp, omegas=w, storage=store, streaming=stream)
                 assert lbm.lbm_validate(p) == 0, (sp, store, stream, lbm.last_error())
