@@ -11,6 +11,9 @@ tests/test_oracle_*.py check it against something other than itself):
 
   Stencil / weights          sec. 2.1 (D2Q9/D3Q15/D3Q19/D3Q27, xi_0 = 0)
         pin: w == M^-1 m0 (sec. 2.4, background equals the weights), isotropy sums
+  weighted_orthogonal_matrix WO-MRT basis (Table 1, sec. 2.3.1): Gram-Schmidt under the weights
+        pin: orthogonality by brute force, D2Q9 / D3Q27 Hermite product forms, unit-rate
+        basis independence, Taylor-Green viscosity
   moment_matrix              eq. DiscreteRawMomentsDef (sec. 2.3.1)
         pin: closed-form 1-D factorisation, w == M^-1 m0, textbook 2nd-order equilibrium
   central_matrix             eq. DiscreteRawMomentsDef for central moments (sec. 2.3.2)
@@ -179,6 +182,21 @@ class Stencil:
 
 
 @lru_cache(maxsize=None)
+def weighted_orthogonal_matrix(st):
+    """Weighted-orthogonal raw-moment basis (the WO-MRT family of Table 1, sec. 2.3.1):
+    Gram-Schmidt of the graded basis, in its order, under <a, b> = sum_i w_i a(xi_i) b(xi_i).
+    Rows of the returned matrix are the new polynomials' monomial coefficients (columns as
+    st.exps); each is its graded counterpart minus a combination of the earlier ones."""
+    G = (st.M * st.w[None, :]) @ st.M.T  # <monomial_j, monomial_l>_w
+    rows = []
+    for k in range(st.q):
+        p = st.P[k].copy()
+        for r in rows:
+            p = p - (p @ G @ r) / (r @ G @ r) * r
+        rows.append(p)
+    return np.array(rows)
+
+
 def stencil(name):
     return Stencil(name)
 
@@ -408,8 +426,18 @@ class Method:
     Rates of the conserved polynomials (1, x, y, z) are ignored (pass-through).  'srt' works
     on the populations themselves with one rate, the common value of the non-conserved rates."""
 
-    def __init__(self, stencil_name, space, omegas, equilibrium="maxwellian", gravity=None, force_model="guo"):
+    def __init__(self, stencil_name, space, omegas, equilibrium="maxwellian", gravity=None, force_model="guo",
+                 basis="graded"):
         self.st = stencil(stencil_name)
+        # polynomial basis of the raw-moment relaxation: the graded one, or its
+        # weighted-orthogonal counterpart (WO-MRT)
+        assert basis in ("graded", "weighted_orthogonal")
+        self.basis = basis
+        if basis == "weighted_orthogonal":
+            assert space == "raw" and stencil_name != "D3Q15"
+            self.P = weighted_orthogonal_matrix(self.st)
+        else:
+            self.P = self.st.P
         self.space = space
         self.omegas = np.asarray(omegas, dtype=np.float64)
         assert self.omegas.shape == (self.st.q,)
@@ -492,8 +520,8 @@ class Method:
             return (1.0 - 0.5 * self.omegas[st.d + 1]) * qF
         om = self.omegas.copy()
         om[st.conserved] = 0.0
-        q = qF @ st.P.T
-        return np.linalg.solve(st.P, ((1.0 - 0.5 * om)[None, :] * q).T).T
+        q = qF @ self.P.T
+        return np.linalg.solve(self.P, ((1.0 - 0.5 * om)[None, :] * q).T).T
 
     def relax(self, q_mono, q_eq_mono):
         """q = P q_mono; q* = q + S (q_eq - q) on non-conserved rows; back to monomials.
@@ -502,12 +530,12 @@ class Method:
         if self.space == "srt":
             om = self.omegas[st.d + 1]
             return q_mono + om * (q_eq_mono - q_mono)
-        q = q_mono @ st.P.T
-        qe = q_eq_mono @ st.P.T
+        q = q_mono @ self.P.T
+        qe = q_eq_mono @ self.P.T
         om = self.omegas.copy()
         om[st.conserved] = 0.0
         qs = q + om[None, :] * (qe - q)
-        return np.linalg.solve(st.P, qs.T).T
+        return np.linalg.solve(self.P, qs.T).T
 
 
 def guo_source(st, u, F):

@@ -577,3 +577,113 @@ def test_kolmogorov_flow_amplitude_second_order(space, model):
         errs.append(abs(amp / (F0 / (nu * k * k)) - 1.0))
     assert errs[1] < 0.01
     assert 3.0 < errs[0] / errs[1] < 5.0
+
+
+# ---------------------------------------------------------------- weighted-orthogonal raw basis
+def _poly_values(st, P):
+    """Values of the polynomials (rows of P over st.exps) at every velocity, by brute force."""
+    xi = st.xi.astype(float)
+    vals = np.zeros((P.shape[0], st.q))
+    for r in range(P.shape[0]):
+        for j, (a, b, c) in enumerate(st.exps):
+            if P[r, j] != 0.0:
+                vals[r] += P[r, j] * xi[:, 0] ** a * xi[:, 1] ** b * xi[:, 2] ** c
+    return vals
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_wo_basis_orthogonal_and_triangular(name):
+    """Every pair of WO polynomials is orthogonal under sum_i w_i a(xi_i) b(xi_i), and each is
+    its graded polynomial plus a combination of the earlier graded ones."""
+    st = O.stencil(name)
+    Pw = O.weighted_orthogonal_matrix(st)
+    v = _poly_values(st, Pw)
+    G = (v * st.w[None, :]) @ v.T
+    off = G - np.diag(np.diag(G))
+    assert np.abs(off).max() < 1e-15
+    T = np.linalg.solve(st.P.T, Pw.T).T  # Pw = T P
+    np.testing.assert_allclose(np.diag(T), 1.0, rtol=0, atol=1e-14)
+    assert np.abs(np.triu(T, 1)).max() < 1e-14
+
+
+def _coeffs(st, terms):
+    out = np.zeros(st.q)
+    for c, e in terms:
+        out[st.eidx[e]] += c
+    return out
+
+
+def test_wo_basis_d2q9_hermite_products():
+    """On D2Q9 the weighted-orthogonal polynomials of orders 3 and 4 are the products of the
+    one-dimensional ones 1, x, x^2 - 1/3 (textbook WO-MRT): x (y^2 - 1/3) and
+    (x^2 - 1/3)(y^2 - 1/3); the trace becomes x^2 + y^2 - 2/3."""
+    st = O.stencil("D2Q9")
+    Pw = O.weighted_orthogonal_matrix(st)
+    names = O.BASIS_NAMES["D2Q9"]
+    want = {
+        "x2+y2": [(1, (2, 0, 0)), (1, (0, 2, 0)), (-2 / 3, (0, 0, 0))],
+        "xy2": [(1, (1, 2, 0)), (-1 / 3, (1, 0, 0))],
+        "x2y": [(1, (2, 1, 0)), (-1 / 3, (0, 1, 0))],
+        "x2y2": [(1, (2, 2, 0)), (-1 / 3, (2, 0, 0)), (-1 / 3, (0, 2, 0)), (1 / 9, (0, 0, 0))],
+    }
+    for nm, terms in want.items():
+        np.testing.assert_allclose(Pw[names.index(nm)], _coeffs(st, terms), rtol=0, atol=1e-15, err_msg=nm)
+
+
+def test_wo_basis_d3q27_top_polynomial_and_trace():
+    """On D3Q27 (a product lattice) the last WO polynomial is (x^2-1/3)(y^2-1/3)(z^2-1/3) and
+    the trace is x^2 + y^2 + z^2 - 1."""
+    st = O.stencil("D3Q27")
+    Pw = O.weighted_orthogonal_matrix(st)
+    t = 1 / 3
+    top = [(1, (2, 2, 2)), (-t, (2, 2, 0)), (-t, (2, 0, 2)), (-t, (0, 2, 2)),
+           (t * t, (2, 0, 0)), (t * t, (0, 2, 0)), (t * t, (0, 0, 2)), (-t ** 3, (0, 0, 0))]
+    np.testing.assert_allclose(Pw[-1], _coeffs(st, top), rtol=0, atol=1e-15)
+    k = O.BASIS_NAMES["D3Q27"].index("x2+y2+z2")
+    np.testing.assert_allclose(Pw[k], _coeffs(st, [(1, (2, 0, 0)), (1, (0, 2, 0)), (1, (0, 0, 2)),
+                                                   (-1, (0, 0, 0))]), rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_wo_mrt_unit_rates_basis_independent_and_shear_rate_not(name):
+    """With every rate 1 the collision sets each non-conserved moment to equilibrium whatever
+    the basis.  With the regularized rates (shear 1.7, the rest 1) the 3-D WO bases differ
+    from the graded ones: their deviatoric fourth-order polynomials are not orthogonal to the
+    shear polynomials before Gram-Schmidt (on D3Q27 <x2y2 - 2x2z2 + y2z2, x2 - y2>_w = -2/9),
+    so they pick up shear parts and the shear deviation reaches the fourth-order moments.
+    D2Q9's one fourth-order polynomial is isotropic and picks up only the trace, whose rate is
+    1, so there R-WO-MRT equals R-MRT.  Mass, momentum and the equilibrium are kept."""
+    st = O.stencil(name)
+    ones = np.ones(st.q)
+    g1, w1 = O.Method(name, "raw", ones), O.Method(name, "raw", ones, basis="weighted_orthogonal")
+    df = _state(g1)
+    np.testing.assert_allclose(O.collide_cells(w1, df, "delta"), O.collide_cells(g1, df, "delta"),
+                               rtol=0, atol=1e-15)
+    om = O.regularized_rates(name, 1.7)
+    g, w = O.Method(name, "raw", om), O.Method(name, "raw", om, basis="weighted_orthogonal")
+    a, b = O.collide_cells(g, df, "delta"), O.collide_cells(w, df, "delta")
+    if name == "D2Q9":
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-15)
+    else:
+        assert np.abs(a - b).max() > 1e-7
+    xi = st.xi.astype(float)
+    np.testing.assert_allclose(b.sum(axis=1), df.sum(axis=1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(b @ xi, df @ xi, rtol=0, atol=1e-15)
+    for form in ("absolute", "zc_absolute"):
+        c = O.collide_cells(w, df + w.f0, form) - w.f0 if form == "absolute" else O.collide_cells(w, df, form)
+        np.testing.assert_allclose(c, b, rtol=0, atol=1e-14)
+    eq = _state(w, noise=0.0)
+    np.testing.assert_allclose(O.collide_cells(w, eq, "delta"), eq, rtol=0, atol=4e-15)
+
+
+def test_taylor_green_decay_rate_wo_mrt():
+    """R-WO-MRT keeps the shear viscosity: the D2Q9 decay rate is 2 nu k^2 within 0.5 %."""
+    omega = 1.2
+    m = O.Method("D2Q9", "raw", O.regularized_rates("D2Q9", omega), basis="weighted_orthogonal")
+    n, steps, every = 32, 200, 20
+    amps = _tgv_amplitude(m, n, 1, 1e-3, steps, every)
+    nu = O.omega_to_viscosity(omega)
+    k = 2 * math.pi / n
+    t = np.arange(0, steps + 1, every)
+    rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
+    assert abs(rate / (2 * nu * k * k) - 1) < 5e-3
