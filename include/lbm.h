@@ -139,6 +139,16 @@ typedef enum { LBM_ARITH_DEVIATION = 0, LBM_ARITH_LITERAL = 1 } lbm_arithmetic;
  * shift the equilibrium velocity to u = (j + F/2) / rho and add (I - S/2) T(S). */
 typedef enum { LBM_FORCE_GUO = 0, LBM_FORCE_HE = 1 } lbm_force_model;
 
+/* Polynomial basis in which raw moments are relaxed (sec. 2.3.1, Table 1).  GRADED: the basis
+ * listed above, every polynomial homogeneous in one order.  WEIGHTED_ORTHOGONAL (WO-MRT): the
+ * Gram-Schmidt orthogonalisation of the graded basis, in its order, under the inner product
+ * <a, b> = sum_i w_i a(xi_i) b(xi_i); omegas[k] is the rate of the k-th orthogonalised
+ * polynomial.  Its polynomials mix orders, so the relaxation couples a moment to lower orders
+ * of the same parity.  WEIGHTED_ORTHOGONAL needs the raw-moment space, the Maxwellian
+ * equilibrium, DEVIATION arithmetic, no body force and D2Q9, D3Q19 or D3Q27
+ * (LBM_EUNSUPPORTED otherwise); with every rate equal to 1 it equals GRADED. */
+typedef enum { LBM_BASIS_GRADED = 0, LBM_BASIS_WEIGHTED_ORTHOGONAL = 1 } lbm_basis;
+
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
  * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS, except
@@ -166,6 +176,7 @@ typedef struct {
   double force[3];        /* constant body force per cell and step (lattice units);           */
                           /* {0, 0, 0} for none.  See lbm_set_force_field.                    */
   int force_model;        /* lbm_force_model of any body force                                */
+  int basis;              /* lbm_basis of the raw-moment relaxation                           */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

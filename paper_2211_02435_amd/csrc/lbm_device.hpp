@@ -267,6 +267,13 @@ struct Relax {
   T b4[6][6];
   T b5[3][3];
   T b6;
+  // cross-order blocks (weighted-orthogonal raw basis), applied to the pre-relaxation
+  // deviations: orders 2 -> 4, 3 -> 5, 2 -> 6 and 4 -> 6; cross == 0 when all vanish
+  T c42[6][6];
+  T c53[3][7];
+  T c62[6];
+  T c64[6];
+  int cross;
 };
 
 // exponent grid indices of each order (3-D); 2-D uses the c = 0 entries
@@ -579,6 +586,34 @@ LBM_HD void he_source(T *src, const T *fe, const T *u, const T *F, T rinv) {
 
 enum ForceModel { FORCE_GUO = 0, FORCE_HE = 1 };
 
+// Cross-order part of the relaxation for a basis whose polynomials mix orders (weighted-
+// orthogonal): x holds c42 v2, c53 v3 and c62 v2 + c64 v4 at the order-4, -5 and -6 entries,
+// from the pre-relaxation deviations v (other entries untouched).
+template <int S, class T>
+LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
+  if constexpr (Lat<S>::D == 3) {
+    sfor<6>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      T acc = T(0);
+      sfor<6>([&](auto K) { acc += R.c42[j][K] * v[o2_3d(K)]; });
+      x[o4_3d(j)] = acc;
+    });
+    if constexpr (S == D3Q27) {
+      sfor<3>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        T acc = T(0);
+        sfor<7>([&](auto K) { acc += R.c53[j][K] * v[o3_3d(K)]; });
+        x[o5_3d(j)] = acc;
+      });
+      T acc = T(0);
+      sfor<6>([&](auto K) { acc += R.c62[K] * v[o2_3d(K)] + R.c64[K] * v[o4_3d(K)]; });
+      x[26] = acc;
+    }
+  } else {
+    x[8] = R.c42[0][0] * v[o2_2d(0)] + R.c42[0][1] * v[o2_2d(1)] + R.c42[0][2] * v[o2_2d(2)];
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // the collision in moment space: m holds dm = M df (exponent-grid order) on entry and the
 // post-collision dm* on exit.  Missing monomials (D3Q19) leave as zero.
@@ -669,7 +704,21 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   };
 
   if constexpr (SP == RAW) {
-    relax<S, REG>(v, R);
+    if constexpr (!REG && S != D3Q15) {
+      if (R.cross) {
+        T x[G];
+        cross_orders<S>(x, v, R);
+        relax<S, false>(v, R);
+        sfor<G>([&](auto E) {
+          constexpr int e = decltype(E)::value;
+          if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 4) v[e] += x[e];
+        });
+      } else {
+        relax<S, false>(v, R);
+      }
+    } else {
+      relax<S, REG>(v, R);
+    }
     add_force(v, false);
   } else {
     // to central moments; with zero orders 0, 1 the order-2 entries are unchanged

@@ -1,6 +1,7 @@
 // Host-only part of the library: parameter validation and the relaxation matrix.
 //
 // Pure host code (no HIP runtime calls), so the CPU test suite can exercise it without a GPU.
+#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -178,7 +179,62 @@ static const int kO5_3[3] = {25, 23, 17};
 static const int kO2_2[3] = {2, 6, 4};
 static const int kO3_2[2] = {7, 5};
 
-lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
+// velocities and weights of a stencil (host copy for the weighted inner product)
+static void host_lattice(int s, std::vector<std::array<int, 3>> *xi, std::vector<double> *w) {
+  const int d = stencil_d(s);
+  for (int z = (d == 3 ? -1 : 0); z <= (d == 3 ? 1 : 0); ++z)
+    for (int y = -1; y <= 1; ++y)
+      for (int x = -1; x <= 1; ++x) {
+        const int n2 = x * x + y * y + z * z;
+        double wt;
+        if (s == LBM_D2Q9) wt = n2 == 0 ? 4.0 / 9 : (n2 == 1 ? 1.0 / 9 : 1.0 / 36);
+        else if (s == LBM_D3Q19) wt = n2 == 0 ? 1.0 / 3 : (n2 == 1 ? 1.0 / 18 : (n2 == 2 ? 1.0 / 36 : 0.0));
+        else if (s == LBM_D3Q15) wt = n2 == 0 ? 2.0 / 9 : (n2 == 1 ? 1.0 / 9 : (n2 == 3 ? 1.0 / 72 : 0.0));
+        else wt = n2 == 0 ? 8.0 / 27 : (n2 == 1 ? 2.0 / 27 : (n2 == 2 ? 1.0 / 54 : 1.0 / 216));
+        if (wt == 0.0) continue;
+        xi->push_back({x, y, z});
+        w->push_back(wt);
+      }
+}
+
+// v^e for a velocity component v in {-1, 0, 1}: 1, v or v^2 by the parity of e
+static double ipow(int v, int e) { return e == 0 ? 1.0 : (e % 2 ? double(v) : double(v * v)); }
+
+// rows of P (monomial coefficients over the present monomials `cols`) orthogonalised in order
+// under <a, b> = sum_i w_i a(xi_i) b(xi_i)
+static void weighted_gram_schmidt(int s, const std::vector<int> &cols, std::vector<double> &P) {
+  const int q = int(cols.size());
+  std::vector<std::array<int, 3>> xi;
+  std::vector<double> w;
+  host_lattice(s, &xi, &w);
+  // G[j][l] = <monomial_j, monomial_l>
+  std::vector<double> G(size_t(q) * q, 0.0);
+  for (int j = 0; j < q; ++j)
+    for (int l = 0; l < q; ++l) {
+      const int ej = cols[j], el = cols[l];
+      double acc = 0.0;
+      for (size_t i = 0; i < xi.size(); ++i)
+        acc += w[i] * ipow(xi[i][0], ej % 3 + el % 3) * ipow(xi[i][1], (ej / 3) % 3 + (el / 3) % 3) *
+               ipow(xi[i][2], ej / 9 + el / 9);
+      G[size_t(j) * q + l] = acc;
+    }
+  auto dot = [&](const double *a, const double *b) {
+    double acc = 0.0;
+    for (int j = 0; j < q; ++j)
+      for (int l = 0; l < q; ++l) acc += a[j] * G[size_t(j) * q + l] * b[l];
+    return acc;
+  };
+  for (int k = 0; k < q; ++k) {
+    double *pk = &P[size_t(k) * q];
+    for (int r = 0; r < k; ++r) {
+      const double *pr = &P[size_t(r) * q];
+      const double c = dot(pk, pr) / dot(pr, pr);
+      for (int j = 0; j < q; ++j) pk[j] -= c * pr[j];
+    }
+  }
+}
+
+lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *out) {
   const int q = stencil_q(s), d = stencil_d(s);
   const std::vector<Poly> B = basis_of(s);
   if (int(B.size()) != q) return fail(LBM_EINVAL, "internal: basis size mismatch");
@@ -196,6 +252,7 @@ lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
   std::vector<double> P(size_t(q) * q, 0.0);
   for (int r = 0; r < q; ++r)
     for (const Term &t : B[r]) P[size_t(r) * q + colof[t.a + 3 * t.b + 9 * t.z]] += t.c;
+  if (basis == LBM_BASIS_WEIGHTED_ORTHOGONAL) weighted_gram_schmidt(s, cols, P);
   std::vector<double> Pinv = P;
   if (!invert(Pinv, q)) return fail(LBM_EINVAL, "internal: singular basis");
   // A = P^-1 S P with the conserved rows (1, x, y, z) at rate 0
@@ -212,14 +269,22 @@ lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
       A[size_t(i) * q + k] = acc;
     }
   auto ord = [&](int e) { return e % 3 + (e / 3) % 3 + e / 9; };
+  // order couplings the kernels apply: within an order, and (weighted-orthogonal basis) from
+  // orders 2 -> 4, 2 -> 6, 4 -> 6, 3 -> 5; columns of the conserved orders meet zero deviations
+  auto coupled = [](int oi, int ok) {
+    return oi == ok || ok <= 1 || (oi == 4 && ok == 2) || (oi == 6 && (ok == 2 || ok == 4)) || (oi == 5 && ok == 3);
+  };
   for (int i = 0; i < q; ++i)
     for (int k = 0; k < q; ++k)
-      if (ord(cols[i]) != ord(cols[k]) && std::fabs(A[size_t(i) * q + k]) > 1e-13)
-        return fail(LBM_EINVAL, "internal: relaxation matrix mixes orders");
+      if (!coupled(ord(cols[i]), ord(cols[k])) && std::fabs(A[size_t(i) * q + k]) > 1e-13)
+        return fail(LBM_EINVAL, "internal: relaxation matrix couples orders the kernels do not");
   auto bval = [&](int ei, int ek) -> double {
     if (colof[ei] < 0 || colof[ek] < 0) return 0.0;
     const double a = A[size_t(colof[ei]) * q + colof[ek]];
-    return (ei == ek ? 1.0 : 0.0) - a;
+    const double b = (ei == ek ? 1.0 : 0.0) - a;
+    // entries below 1e-14 are the round-off of exact zeros (a rate of 1, an orthogonal pair):
+    // kept exactly zero, as the regularized-kernel test below treats them
+    return std::fabs(b) < 1e-14 ? 0.0 : b;
   };
   std::memset(out, 0, sizeof(*out));
   if (d == 3) {
@@ -232,18 +297,34 @@ lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out) {
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) out->b5[j][k] = bval(kO5_3[j], kO5_3[k]);
     out->b6 = bval(26, 26);
+    for (int j = 0; j < 6; ++j)
+      for (int k = 0; k < 6; ++k) out->c42[j][k] = bval(kO4_3[j], kO2_3[k]);
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 7; ++k) out->c53[j][k] = bval(kO5_3[j], kO3_3[k]);
+    for (int k = 0; k < 6; ++k) {
+      out->c62[k] = bval(26, kO2_3[k]);
+      out->c64[k] = bval(26, kO4_3[k]);
+    }
   } else {
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) out->b2[j][k] = bval(kO2_2[j], kO2_2[k]);
     for (int j = 0; j < 2; ++j)
       for (int k = 0; k < 2; ++k) out->b3[j][k] = bval(kO3_2[j], kO3_2[k]);
     out->b4[0][0] = bval(8, 8);
+    for (int k = 0; k < 3; ++k) out->c42[0][k] = bval(8, kO2_2[k]);
   }
-  // regularized: every block of order >= 3 is zero (all those rates equal 1)
+  double cmax = 0.0;
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) cmax = std::fmax(cmax, std::fabs(out->c42[j][k]));
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 7; ++k) cmax = std::fmax(cmax, std::fabs(out->c53[j][k]));
+  for (int k = 0; k < 6; ++k) cmax = std::fmax(cmax, std::fmax(std::fabs(out->c62[k]), std::fabs(out->c64[k])));
+  out->cross = cmax > 1e-14;
+  // regularized: every block into an order >= 3 (from the orders >= 2 the kernels use) is zero
   double hi = 0.0;
   for (int i = 0; i < q; ++i)
     for (int k = 0; k < q; ++k)
-      if (ord(cols[i]) >= 3) hi = std::fmax(hi, std::fabs(bval(cols[i], cols[k])));
+      if (ord(cols[i]) >= 3 && ord(cols[k]) >= 2) hi = std::fmax(hi, std::fabs(bval(cols[i], cols[k])));
   out->regularized = hi < 1e-14;
   return LBM_OK;
 }
@@ -282,6 +363,18 @@ lbm_status validate(const lbm_params *p) {
   if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
     return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");
   if (p->stencil == LBM_D2Q9 && p->nz != 1) return fail(LBM_EUNSUPPORTED, "D2Q9 requires nz == 1");
+  if (p->basis != LBM_BASIS_GRADED && p->basis != LBM_BASIS_WEIGHTED_ORTHOGONAL)
+    return fail(LBM_EINVAL, "basis out of range");
+  if (p->basis == LBM_BASIS_WEIGHTED_ORTHOGONAL) {
+    if (p->space != LBM_SPACE_RAW) return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis is a raw-moment basis");
+    if (p->equilibrium != LBM_EQ_MAXWELLIAN)
+      return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis runs with the Maxwellian equilibrium");
+    if (p->arithmetic != LBM_ARITH_DEVIATION)
+      return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis runs with the deviation arithmetic");
+    if (p->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "no weighted-orthogonal basis for D3Q15");
+    if (p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0)
+      return fail(LBM_EUNSUPPORTED, "no body force with the weighted-orthogonal basis");
+  }
   if (p->stencil == LBM_D3Q15) {
     if (p->space != LBM_SPACE_RAW && p->space != LBM_SPACE_SRT)
       return fail(LBM_EUNSUPPORTED, "D3Q15 is implemented in raw-moment space and SRT");
@@ -365,7 +458,7 @@ extern "C" lbm_status lbm_validate(const lbm_params *p) {
   const lbm_status s = validate(p);
   if (s != LBM_OK) return s;
   RelaxHost r;
-  return relaxation_blocks(p->stencil, p->omegas, &r);
+  return relaxation_blocks(p->stencil, p->basis, p->omegas, &r);
 }
 
 extern "C" lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes) {

@@ -16,6 +16,14 @@ struct RelaxHost {
   double b4[6][6];
   double b5[3][3];
   double b6;
+  // cross-order blocks of a basis whose polynomials mix orders (weighted-orthogonal):
+  // dm*_4 += c42 dm_2, dm*_5 += c53 dm_3, dm*_6 += c62 . dm_2 + c64 . dm_4 (pre-relaxation
+  // deviations; the conserved orders carry none without a force)
+  double c42[6][6];
+  double c53[3][7];
+  double c62[6];
+  double c64[6];
+  bool cross;        // some cross-order block is nonzero
   bool regularized;  // every block of order >= 3 vanishes (all those rates equal 1)
 };
 
@@ -37,6 +45,6 @@ int resolve_layout(const lbm_params *p);
 void storage_strides(const lbm_params *p, uint64_t *ps, uint64_t *zs, uint64_t *ys, uint64_t *elems);
 constexpr size_t kDefaultPlanePadBytes = 0;
 lbm_status validate(const lbm_params *p);
-lbm_status relaxation_blocks(int s, const double *omegas, RelaxHost *out);
+lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *out);
 
 }  // namespace lbm

@@ -238,6 +238,15 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   for (int j = 0; j < 3; ++j)
     for (int k = 0; k < 3; ++k) a.R.b5[j][k] = CT(c->R.b5[j][k]);
   a.R.b6 = CT(c->R.b6);
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) a.R.c42[j][k] = CT(c->R.c42[j][k]);
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 7; ++k) a.R.c53[j][k] = CT(c->R.c53[j][k]);
+  for (int k = 0; k < 6; ++k) {
+    a.R.c62[k] = CT(c->R.c62[k]);
+    a.R.c64[k] = CT(c->R.c64[k]);
+  }
+  a.R.cross = c->R.cross ? 1 : 0;
   return a;
 }
 
@@ -426,7 +435,7 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   c->nz = int(p->nz);
   c->ncells = uint32_t(p->nx * p->ny * p->nz);
   c->elem = storage_bytes(p->storage);
-  s = relaxation_blocks(c->s, c->omegas.data(), &c->R);
+  s = relaxation_blocks(c->s, p->basis, c->omegas.data(), &c->R);
   if (s != LBM_OK) {
     delete c;
     return s;
@@ -616,6 +625,8 @@ extern "C" lbm_status lbm_set_force_field(lbm_ctx *c, const double *F) {
   if (c->eq != MAXWELL) return fail(LBM_EUNSUPPORTED, "the body force is implemented with the Maxwellian equilibrium");
   if (c->literal) return fail(LBM_EUNSUPPORTED, "the body force runs with the deviation arithmetic");
   if (c->transform == LBM_TRANSFORM_DENSE_MFMA) return fail(LBM_EUNSUPPORTED, "no body force in the MFMA ablation");
+  if (c->R.cross || c->p.basis != LBM_BASIS_GRADED)
+    return fail(LBM_EUNSUPPORTED, "no body force with the weighted-orthogonal basis");
   const size_t n = 3 * size_t(c->ncells);
   std::vector<double> h(n);
   if (is_device_ptr(F)) HIPCHECK(hipMemcpy(h.data(), F, n * sizeof(double), hipMemcpyDeviceToHost), "force copy");
@@ -800,10 +811,10 @@ extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
     return fail(LBM_EINVAL, "transform out of range");
   if (transform == LBM_TRANSFORM_DENSE_MFMA) {
     if (c->s != LBM_D3Q27 || c->pattern != LBM_STREAM_PULL || c->eq != MAXWELL || c->space == SRT || c->literal ||
-        forced(c))
+        forced(c) || c->R.cross)
       return fail(LBM_EUNSUPPORTED,
                   "the MFMA ablation covers D3Q27 moment spaces, pull streaming, Maxwellian equilibrium, "
-                  "deviation arithmetic");
+                  "deviation arithmetic, the graded basis");
     if (c->bx * c->by > 256 || (c->bx * c->by) % 64 != 0)
       return fail(LBM_EUNSUPPORTED, "the MFMA ablation needs blocks of 64..256 threads (whole waves)");
   }
@@ -1199,6 +1210,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
     return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the deviation arithmetic");
   if (common->force[0] != 0.0 || common->force[1] != 0.0 || common->force[2] != 0.0)
     return fail(LBM_EUNSUPPORTED, "the batched ensemble runs without a body force");
+  if (common->basis != LBM_BASIS_GRADED) return fail(LBM_EUNSUPPORTED, "the batched ensemble uses the graded basis");
   lbm_batch *b = new lbm_batch();
   b->p = *common;
   b->s = common->stencil;
@@ -1219,7 +1231,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
     pk.omegas = omegas + size_t(k) * b->q;
     pk.n_omegas = b->q;
     lbm_status s = validate(&pk);
-    if (s == LBM_OK) s = relaxation_blocks(b->s, pk.omegas, &rh[k]);
+    if (s == LBM_OK) s = relaxation_blocks(b->s, pk.basis, pk.omegas, &rh[k]);
     if (s != LBM_OK) {
       delete b;
       return fail(s, "box " + std::to_string(k) + ": " + g_last_error);

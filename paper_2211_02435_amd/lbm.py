@@ -23,6 +23,7 @@ STREAMING = {"pull": 0, "aa": 1, "esoteric": 2, "twist": 3}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
 FORCE_MODELS = {"guo": 0, "he": 1}
+BASES = {"graded": 0, "weighted_orthogonal": 1}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27, "D3Q15": 15}
 # order of every polynomial of the bases documented in lbm.h (one rate per entry of omegas)
 BASIS_ORDERS = {
@@ -54,7 +55,8 @@ class LbmParams(ctypes.Structure):
                 ("gravity", c_double), ("nx", c_int64), ("ny", c_int64), ("nz", c_int64),
                 ("periodic", c_int * 3), ("storage", c_int), ("streaming", c_int),
                 ("buffers", c_void_p * 2), ("buffer_bytes", c_size_t), ("stream", c_void_p),
-                ("layout", c_int), ("arithmetic", c_int), ("force", c_double * 3), ("force_model", c_int)]
+                ("layout", c_int), ("arithmetic", c_int), ("force", c_double * 3), ("force_model", c_int),
+                ("basis", c_int)]
 
 
 class LbmError(RuntimeError):
@@ -149,7 +151,7 @@ def _dptr(a):
 
 def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", equilibrium="maxwellian",
                 eq_form="default", gravity=0.0, zero_centered=1, layout="auto", arithmetic="deviation",
-                force=(0.0, 0.0, 0.0), force_model="guo"):
+                force=(0.0, 0.0, 0.0), force_model="guo", basis="graded"):
     p = LbmParams()
     check(load().lbm_params_default(ctypes.byref(p)))
     p.stencil = STENCILS[stencil]
@@ -170,6 +172,7 @@ def make_params(stencil, space, omegas, dims, storage="f32", streaming="pull", e
     for d in range(3):
         p.force[d] = float(force[d])
     p.force_model = FORCE_MODELS[force_model]
+    p.basis = BASES[basis]
     return p
 
 
@@ -191,7 +194,8 @@ class Lattice:
 
     def __init__(self, stencil, space, omegas, dims, storage="f32", streaming="pull",
                  equilibrium="maxwellian", eq_form="default", gravity=0.0, torch_buffers=True, layout="auto",
-                 zero_centered=True, arithmetic="deviation", force=(0.0, 0.0, 0.0), force_model="guo"):
+                 zero_centered=True, arithmetic="deviation", force=(0.0, 0.0, 0.0), force_model="guo",
+                 basis="graded"):
         import torch
         self.lib = load()
         self.stencil, self.space, self.storage, self.streaming = stencil, space, storage, streaming
@@ -200,7 +204,7 @@ class Lattice:
         self.ncells = self.dims[0] * self.dims[1] * self.dims[2]
         p = make_params(stencil, space, omegas, dims, storage, streaming, equilibrium, eq_form, gravity,
                         zero_centered=1 if zero_centered else 0, layout=layout, arithmetic=arithmetic,
-                        force=force, force_model=force_model)
+                        force=force, force_model=force_model, basis=basis)
         self._torch_stream = torch.cuda.Stream()
         p.stream = c_void_p(self._torch_stream.cuda_stream)
         self._bufs = []

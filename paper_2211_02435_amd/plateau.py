@@ -16,9 +16,9 @@ This module runs that experiment on the GPU through the library:
     eq. MrtUpdateAbsoluteFromZeroCentered, the delta form being inadmissible);
   * an ablation column subtracts the background from the absolute equilibrium numerically
     (LBM_ARITH_LITERAL with the delta form) to show what that cancellation is worth;
-  * R-MRT uses the library's graded raw-moment basis instead of the weighted-orthogonal one:
-    with every rate equal to 1 the relaxation sets each non-conserved moment to its
-    equilibrium value whatever the basis;
+  * R-WO-MRT: with every rate equal to 1 the weighted-orthogonal raw basis
+    (LBM_BASIS_WEIGHTED_ORTHOGONAL) and the graded one give identical, all-zero relaxation
+    blocks, so the runs take the graded basis, which the literal forms also accept;
   * the vortex does not vary along z and every cell is updated by the same arithmetic, so all
     z-planes stay bit-identical and an L x L x nz box gives the E/E0 of the L^3 box for any nz;
   * with FP16 storage (FP32 arithmetic) the literal forms do not exist, so the comparison is
@@ -39,7 +39,7 @@ import numpy as np
 import lbm_workloads as W  # seeded synthetic inputs (repository root)
 from . import lbm
 
-METHODS = [("SRT", "srt"), ("R-MRT (raw)", "raw"), ("R-CM", "central"), ("R-K", "cumulant")]
+METHODS = [("SRT", "srt"), ("R-WO-MRT", "raw"), ("R-CM", "central"), ("R-K", "cumulant")]
 COLUMNS = [
     ("absolute storage", dict(zero_centered=False, eq_form="default", arithmetic="literal")),
     ("zero-centred, f_eq", dict(zero_centered=True, eq_form="absolute", arithmetic="literal")),

@@ -160,6 +160,30 @@ def test_d3q15_parameter_sets():
                                      storage="f32")) % (2 * 15 * 256) == 0
 
 
+def test_weighted_orthogonal_basis_parameter_sets():
+    """The weighted-orthogonal basis is accepted for raw-moment MRT on D2Q9, D3Q19 and D3Q27
+    (any storage and streaming pattern) and rejected elsewhere."""
+    for st in ("D2Q9", "D3Q19", "D3Q27"):
+        om = O.regularized_rates(st, 1.6)
+        for store in ("f64", "f32", "f16"):
+            for stream in ("pull", "aa", "esoteric", "twist"):
+                p = _p(stencil=st, space="raw", omegas=om, storage=store, streaming=stream,
+                       basis="weighted_orthogonal")
+                assert lbm.lbm_validate(p) == 0, (st, store, stream, lbm.last_error())
+    om = O.regularized_rates("D3Q27", 1.6)
+    for kw in (dict(space="central"), dict(space="cumulant"), dict(space="srt", omegas=np.r_[np.zeros(4), np.full(23, 1.6)]),
+               dict(space="raw", arithmetic="literal"), dict(space="raw", force=(1e-5, 0, 0)),
+               dict(stencil="D3Q15", space="raw", omegas=O.regularized_rates("D3Q15", 1.6)),
+               dict(stencil="D2Q9", space="raw", omegas=O.regularized_rates("D2Q9", 1.6), equilibrium="swe",
+                    gravity=0.1)):
+        kw.setdefault("omegas", om)
+        assert lbm.lbm_validate(_p(basis="weighted_orthogonal", **kw)) == lbm.LBM_EUNSUPPORTED, kw
+        assert lbm.last_error() != ""
+    p = _p(space="raw", omegas=om)
+    p.basis = 2
+    assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+
+
 def test_params_struct_layout_matches_the_header(tmp_path):
     """The ctypes mirror of lbm_params has the C compiler's size and field offsets."""
     fields = [f[0] for f in lbm.LbmParams._fields_]

@@ -1,5 +1,5 @@
 """Round-off plateau of the Taylor-Green energy decay (sec. 5.1), at the paper's configuration:
-D3Q27, u0 = 0.25, nu = 1/6 (omega = 1), L = 256, 200 000 steps, FP64, for SRT, R-MRT, R-CM
+D3Q27, u0 = 0.25, nu = 1/6 (omega = 1), L = 256, 200 000 steps, FP64, for SRT, R-WO-MRT, R-CM
 and R-K with every admissible combination of storage format and equilibrium form
 (paper_2211_02435_amd.plateau).
 
@@ -62,7 +62,7 @@ def test_plateau_ordering_of_the_storage_and_equilibrium_forms(space):
     d = zero-centred with the equilibrium deviation subtracted numerically (literal
     eq. MrtUpdateGeneralDeviationOnly, an ablation); v = the deviation arithmetic, in which the
     background cancels before evaluation as it does in a symbolically derived delta-equilibrium
-    (the paper's delta column for SRT, R-MRT and R-CM; for R-K the deviation-organised form of
+    (the paper's delta column for SRT, R-WO-MRT and R-CM; for R-K the deviation-organised form of
     eq. MrtUpdateAbsoluteFromZeroCentered)."""
     nu = 1.0 / 6.0
     k = 2.0 * math.pi / N
