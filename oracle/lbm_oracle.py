@@ -446,7 +446,7 @@ class Method:
         assert force_model in ("guo", "he")
         self.force_model = force_model
         if stencil_name == "D3Q15":
-            assert space in ("raw", "srt") and equilibrium == "maxwellian"
+            assert equilibrium == "maxwellian"
         if space == "srt":
             assert equilibrium == "maxwellian"
             rest = self.omegas[self.st.d + 1:]

@@ -14,7 +14,8 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")
 
 CASES = [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
          ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
-         ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant"), ("D3Q15", "raw")]
+         ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant"),
+         ("D3Q15", "raw"), ("D3Q15", "central"), ("D3Q15", "cumulant")]
 
 
 def _general_rates(name, seed):
@@ -226,6 +227,26 @@ def test_d3q15_polynomial_equilibrium_fourth_moment():
     for a, b in ((0, 1), (0, 2), (1, 2)):
         mom = sum(feq[i] * st.xi[i, a] ** 2 * st.xi[i, b] ** 2 for i in range(st.q))
         assert abs(mom - want) < 1e-16
+
+
+def test_d3q15_central_equilibrium_carries_the_maxwellian_on_each_representative():
+    """D3Q15 in central-moment space: the equilibrium populations have the Maxwellian's raw
+    moments on the 15 representative monomials, e.g. sum f xi_x^2 xi_y^2 =
+    rho (1/9 + (ux^2 + uy^2)/3 + ux^2 uy^2) and sum f xi_x^2 xi_z = rho uz (1/3 + ux^2)
+    (moments of the continuous Maxwellian, worked out by hand); the other members of a class
+    follow the representative, so x^2 z^2 takes the x^2 y^2 value."""
+    st = O.stencil("D3Q15")
+    m = O.Method("D3Q15", "central", O.regularized_rates("D3Q15", 1.3))
+    rho = np.array([1.03])
+    ux, uy, uz = 0.04, -0.03, 0.02
+    feq = O.equilibrium_populations(m, rho, np.array([[ux, uy, uz]]))[0]
+    xi = st.xi.astype(float)
+    mom = lambda a, b, c: (feq * xi[:, 0] ** a * xi[:, 1] ** b * xi[:, 2] ** c).sum()
+    want22 = 1.03 * (1 / 9 + (ux * ux + uy * uy) / 3 + ux * ux * uy * uy)
+    assert abs(mom(2, 2, 0) - want22) < 4e-16
+    assert abs(mom(2, 0, 2) - want22) < 4e-16
+    assert abs(mom(2, 0, 1) - 1.03 * uz * (1 / 3 + ux * ux)) < 4e-16
+    assert abs(mom(2, 0, 0) - 1.03 * (1 / 3 + ux * ux)) < 4e-16
 
 
 def test_d3q15_raw_moment_bgk_equals_srt():
@@ -474,6 +495,21 @@ def test_taylor_green_decay_d3q15_raw():
     rate of the velocity amplitude is 2 nu k^2 within 1 %."""
     omega = 1.1
     m = O.Method("D3Q15", "raw", O.regularized_rates("D3Q15", omega))
+    n = 32
+    amps = _tgv_amplitude(m, n, 1, 1e-3, 160, 20)
+    nu = O.omega_to_viscosity(omega)
+    k = 2 * math.pi / n
+    t = np.arange(0, 161, 20)
+    rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
+    assert abs(rate / (2 * nu * k * k) - 1) < 1e-2
+
+
+@pytest.mark.parametrize("space", ["central", "cumulant"])
+def test_taylor_green_decay_d3q15_central_and_cumulant(space):
+    """z-invariant Taylor-Green vortex on D3Q15 with regularized central-moment and cumulant
+    rates: the decay rate is 2 nu k^2 within 1 %."""
+    omega = 1.1
+    m = O.Method("D3Q15", space, O.regularized_rates("D3Q15", omega))
     n = 32
     amps = _tgv_amplitude(m, n, 1, 1e-3, 160, 20)
     nu = O.omega_to_viscosity(omega)
