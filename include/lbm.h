@@ -41,8 +41,11 @@
  *     D3Q15: 1, x, y, z, xy, xz, yz, x2-y2, x2-z2, x2+y2+z2, xyz, xy2, x2y, x2z, x2y2, where
  *            xy2 stands for its class on the lattice (xy2 = xz2 = xy2z2 there), x2y for
  *            (x2y, yz2, x2yz2), x2z for (x2z, y2z, x2y2z) and x2y2 for the corner indicator
- *            (x2y2 = x2z2 = y2z2 = x2y2z2); D3Q15 runs in raw-moment space and SRT, with the
- *            second-order polynomial equilibrium (it cannot carry the Maxwellian's moments).
+ *            (x2y2 = x2z2 = y2z2 = x2y2z2).  In raw-moment space and SRT D3Q15 takes the
+ *            second-order polynomial equilibrium (its raw classes cannot carry the
+ *            Maxwellian's raw moments); in central-moment and cumulant space the
+ *            Maxwellian's central moments are imposed on these 15 monomials, a set closed
+ *            under lowering exponents and hence under the binomial shift.
  *     Rates of the conserved polynomials 1, x, y, z are ignored.
  *   Equilibria: LBM_EQ_MAXWELLIAN is the continuous Maxwellian of sec. 2.4; its raw moments
  *     are truncated at second order in u (sec. 4.3), its central moments and cumulants are

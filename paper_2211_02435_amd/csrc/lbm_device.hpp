@@ -649,18 +649,21 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   } else if constexpr (EQ == SWEK) {
     static_assert(S == D2Q9, "the shallow-water equilibria are two-dimensional");
     swek_meq_dev(meq, drho, rho, u, grav);
-  } else if constexpr (S == D3Q15) {
-    // D3Q15 cannot carry the Maxwellian's moments: its equilibrium is the second-order
-    // polynomial one, taken to moments by the Chimera (consistent within every class)
-    static_assert(SP == RAW, "D3Q15 is implemented in raw-moment space (and SRT)");
+  } else if constexpr (S == D3Q15 && SP == RAW) {
+    // D3Q15's raw monomial classes cannot carry the Maxwellian's raw moments: its raw
+    // equilibrium is the second-order polynomial one, taken to moments by the Chimera
+    // (consistent within every class)
     sfor<G>([&](auto E) { meq[E] = T(0); });
     srt_feq_dev<S>(meq, drho, rho, u);
     chimera_forward<S>(meq);
   } else {
+    // the Maxwellian's value on each monomial of the set; on D3Q15 (central moments and
+    // cumulants) every other member of a class takes its representative's value, which
+    // keeps the grid consistent for the inverse Chimera (rep(e) < e is already set)
     sfor<G>([&](auto E) {
       constexpr int e = decltype(E)::value;
       if constexpr (Lat<S>::has_mono_e(e)) meq[e] = meq_dev<e, SP == RAW>(drho, rho, u, uu);
-      else meq[e] = T(0);
+      else meq[e] = S == D3Q15 ? meq[Lat<S>::rep(e)] : T(0);
     });
     meq[EX] = jx;
     meq[EY] = jy;
@@ -808,7 +811,7 @@ LBM_HD void equilibrium_dev(T *g, T drho, const T *u, T grav) {
   } else if constexpr (EQ == SWEK) {
     swek_meq_dev(g, drho, rho, u, grav);
     chimera_inverse<S>(g);
-  } else if constexpr (SP == SRT || S == D3Q15) {
+  } else if constexpr (SP == SRT || (S == D3Q15 && SP == RAW)) {
     sfor<G>([&](auto E) { g[E] = T(0); });
     srt_feq_dev<S>(g, drho, rho, u);
   } else {
@@ -816,7 +819,7 @@ LBM_HD void equilibrium_dev(T *g, T drho, const T *u, T grav) {
     sfor<G>([&](auto E) {
       constexpr int e = decltype(E)::value;
       if constexpr (Lat<S>::has_mono_e(e)) g[e] = meq_dev<e, SP == RAW>(drho, rho, u, uu);
-      else g[e] = T(0);
+      else g[e] = S == D3Q15 ? g[Lat<S>::rep(e)] : T(0);
     });
     chimera_inverse<S>(g);
   }

@@ -376,10 +376,8 @@ lbm_status validate(const lbm_params *p) {
       return fail(LBM_EUNSUPPORTED, "no body force with the weighted-orthogonal basis");
   }
   if (p->stencil == LBM_D3Q15) {
-    if (p->space != LBM_SPACE_RAW && p->space != LBM_SPACE_SRT)
-      return fail(LBM_EUNSUPPORTED, "D3Q15 is implemented in raw-moment space and SRT");
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
-      return fail(LBM_EUNSUPPORTED, "D3Q15 takes the polynomial Maxwellian equilibrium");
+      return fail(LBM_EUNSUPPORTED, "D3Q15 takes the Maxwellian equilibrium");
     if (p->arithmetic != LBM_ARITH_DEVIATION)
       return fail(LBM_EUNSUPPORTED, "D3Q15 runs with the deviation arithmetic");
   }

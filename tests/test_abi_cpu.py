@@ -138,20 +138,19 @@ def test_srt_and_literal_parameter_sets():
 
 
 def test_d3q15_parameter_sets():
-    """D3Q15 runs in raw-moment space and as SRT, with the polynomial equilibrium, on every
-    storage and streaming pattern; the other spaces, the shallow-water equilibria and the
-    literal arithmetic are rejected."""
+    """D3Q15 runs in every space with the Maxwellian equilibrium, on every storage and
+    streaming pattern; the shallow-water equilibria, the literal arithmetic and the
+    weighted-orthogonal basis are rejected."""
     om = O.regularized_rates("D3Q15", 1.6)
     srt = np.r_[np.zeros(4), np.full(11, 1.6)]
     for store in ("f64", "f32", "f16"):
         for stream in ("pull", "aa", "esoteric", "twist"):
-            for sp, w in (("raw", om), ("srt", srt)):
+            for sp, w in (("raw", om), ("srt", srt), ("central", om), ("cumulant", om)):
                 p = _p(stencil="D3Q15", space=sp, omegas=w, storage=store, streaming=stream)
                 assert lbm.lbm_validate(p) == 0, (sp, store, stream, lbm.last_error())
     assert lbm.lbm_validate(_p(stencil="D3Q15", space="raw", omegas=om, force=(1e-5, 0, 0))) == 0
     assert lbm.lbm_validate(_p(stencil="D3Q15", space="raw", omegas=om, zero_centered=0)) == 0
-    for kw in (dict(space="central"), dict(space="cumulant"),
-               dict(space="raw", arithmetic="literal"),
+    for kw in (dict(space="raw", arithmetic="literal"),
                dict(space="raw", equilibrium="swe", gravity=0.1)):
         assert lbm.lbm_validate(_p(stencil="D3Q15", omegas=om, **kw)) == lbm.LBM_EUNSUPPORTED, kw
         assert lbm.last_error() != ""

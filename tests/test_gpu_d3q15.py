@@ -1,9 +1,10 @@
-"""D3Q15 on the GPU (raw-moment MRT and SRT with the polynomial equilibrium) against the FP64
-oracle, through the C ABI.
+"""D3Q15 on the GPU (raw moments and SRT with the polynomial equilibrium, central moments and
+cumulants with the Maxwellian) against the FP64 oracle, through the C ABI.
 
 D3Q15 keeps the rest, face and corner velocities of D3Q27.  Its moment set has one monomial per
-exponent-parity class of the mixed monomials (sec. 2.3), so the kernels collide on the
-15 representatives and copy each representative into the rest of its class before the inverse
+exponent-parity class of the mixed monomials (sec. 2.3); the set is closed under lowering
+exponents, so the binomial shift maps it to itself, and the kernels collide on the 15
+representatives and copy each representative into the rest of its class before the inverse
 transform.
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 4 steps from a non-equilibrium state (pull,
@@ -46,7 +47,8 @@ def _noisy_state(m, dims=RAGGED3, seed=11):
     return df + W.random_perturbation(m.st.q, (nz, ny, nx), seed=seed + 1, scale=2e-4)
 
 
-@pytest.mark.parametrize("space,kind", [("raw", "reg"), ("raw", "gen"), ("srt", "gen")])
+@pytest.mark.parametrize("space,kind", [("raw", "reg"), ("raw", "gen"), ("srt", "gen"), ("central", "reg"),
+                                        ("central", "gen"), ("cumulant", "reg"), ("cumulant", "gen")])
 @pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
 def test_d3q15_sweep_fp64_matches_oracle(space, kind, streaming, layout):
@@ -61,7 +63,7 @@ def test_d3q15_sweep_fp64_matches_oracle(space, kind, streaming, layout):
     assert err <= 1e-13
 
 
-@pytest.mark.parametrize("space", ["raw", "srt"])
+@pytest.mark.parametrize("space", ["raw", "srt", "central", "cumulant"])
 @pytest.mark.parametrize("streaming", ["pull", "esoteric", "twist"])
 def test_d3q15_fp32_matches_oracle(space, streaming):
     om = _rates(space, "gen")
@@ -75,7 +77,7 @@ def test_d3q15_fp32_matches_oracle(space, streaming):
     assert err <= 1.5e-8
 
 
-@pytest.mark.parametrize("space", ["raw", "srt"])
+@pytest.mark.parametrize("space", ["raw", "srt", "central", "cumulant"])
 def test_d3q15_init_and_macroscopic_match_oracle(space):
     om = _rates(space, "reg")
     m = O.Method("D3Q15", space, om)
@@ -107,7 +109,7 @@ def test_d3q15_streaming_index_maps_bit_exact(streaming, n, layout):
     np.testing.assert_array_equal(lat.lbm_get_populations(), want)
 
 
-@pytest.mark.parametrize("space", ["raw", "srt"])
+@pytest.mark.parametrize("space", ["raw", "srt", "central", "cumulant"])
 @pytest.mark.parametrize("model", ["guo", "he"])
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
 def test_d3q15_forced_fp64_matches_oracle(space, model, streaming):
@@ -129,14 +131,15 @@ def test_d3q15_forced_fp64_matches_oracle(space, model, streaming):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
-def test_d3q15_taylor_green_decay(storage):
-    """z-invariant Taylor-Green vortex on 64 x 64 x 2 with regularized raw-moment rates: the
-    fitted decay rate of the velocity amplitude is 2 nu k^2 within 1 %."""
+@pytest.mark.parametrize("space", ["raw", "cumulant"])
+def test_d3q15_taylor_green_decay(storage, space):
+    """z-invariant Taylor-Green vortex on 64 x 64 x 2 with regularized rates: the fitted decay
+    rate of the velocity amplitude is 2 nu k^2 within 1 %."""
     omega = 1.1
     om = O.regularized_rates("D3Q15", omega)
     n, nz = 64, 2
     rho, u = W.tgv2d_fields(n, n, nz, u0=0.02)
-    lat = lbm.Lattice("D3Q15", "raw", om, (n, n, nz), storage=storage)
+    lat = lbm.Lattice("D3Q15", space, om, (n, n, nz), storage=storage)
     lat.lbm_init_equilibrium(rho, u)
     k = 2 * math.pi / n
     x = np.arange(n)
@@ -151,5 +154,5 @@ def test_d3q15_taylor_green_decay(storage):
     rate = -np.polyfit(t[1:], np.log(amps[1:]), 1)[0]
     nu = O.omega_to_viscosity(omega)
     rel = abs(rate / (2 * nu * k * k) - 1)
-    print("D3Q15 %s Taylor-Green decay-rate rel. error %.3e" % (storage, rel))
+    print("D3Q15 %s %s Taylor-Green decay-rate rel. error %.3e" % (space, storage, rel))
     assert rel < 1e-2
