@@ -188,7 +188,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--layout", default="auto", choices=["auto", "planes", "rows"])
-    ap.add_argument("--streaming", default="pull", choices=["pull", "aa", "esoteric", "twist"])
+    ap.add_argument("--streaming", default="pull", choices=["pull", "push", "aa", "esoteric", "twist"])
     ap.add_argument("--rates", default="regularized", choices=["regularized", "general"],
                     help="general: every rate of order >= 3 set to 1.3 (non-regularized kernels)")
     ap.add_argument("--transform", default="chimera", choices=["chimera", "dense_mfma"],

@@ -106,7 +106,8 @@ typedef enum { LBM_EQFORM_DEFAULT = 0, LBM_EQFORM_ABSOLUTE = 1, LBM_EQFORM_DELTA
 /* Storage precision of the populations.  Compute precision is FP64 for F64 storage and FP32
  * for F32 and F16 storage.  Initialisation and every reader compute in FP64. */
 typedef enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2 } lbm_storage;
-/* PULL: two arrays, each step gathers f_i(x) from x - xi_i.  AA: one array, in place
+/* PULL: two arrays, each step gathers f_i(x) from x - xi_i.  PUSH: two arrays, each step
+ * reads the cell's own populations and scatters f*_i to x + xi_i.  AA: one array, in place
  * (even steps read and write the cell's own slots, odd steps read from x - xi_i and write to
  * x + xi_i); sec. 4.4. */
 /* ESOTERIC_PULL: one array, in place (sec. 4.4): every step a cell touches its own slots and
@@ -121,7 +122,8 @@ typedef enum {
   LBM_STREAM_PULL = 0,
   LBM_STREAM_AA = 1,
   LBM_STREAM_ESOTERIC_PULL = 2,
-  LBM_STREAM_ESOTERIC_TWIST = 3
+  LBM_STREAM_ESOTERIC_TWIST = 3,
+  LBM_STREAM_PUSH = 4
 } lbm_streaming;
 
 /* How the collision's arithmetic is organised.  DEVIATION: every intermediate is a deviation

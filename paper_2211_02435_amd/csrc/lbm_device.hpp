@@ -42,7 +42,7 @@ enum EqId { MAXWELL = 0, SWE = 1, SWEK = 2 };
 // PULL: gather from x - xi.  AA_EVEN: own slots, write to the opposite slot.
 // AA_ODD: read opposite slot at x - xi, write own slot at x + xi.
 // ESO_EVEN / ESO_ODD: the Esoteric-Pull in-place pattern (see lbm_kernels.hpp).
-enum PatternId { PULL = 0, AA_EVEN = 1, AA_ODD = 2, ESO_EVEN = 3, ESO_ODD = 4, TW_EVEN = 5, TW_ODD = 6 };
+enum PatternId { PULL = 0, AA_EVEN = 1, AA_ODD = 2, ESO_EVEN = 3, ESO_ODD = 4, TW_EVEN = 5, TW_ODD = 6, PUSH = 7 };
 // Layout of the canonical state df(t) in a buffer, for readers and writers.
 enum GatherId { G_SHIFTED = 0, G_NATURAL = 1, G_AA_ODD = 2, G_ESO_EVEN = 3, G_ESO_ODD = 4, G_TW_EVEN = 5, G_TW_ODD = 6 };
 

@@ -1,7 +1,7 @@
 // HIP kernels of the lattice Boltzmann library (gfx950).
 //
 // sweep_kernel   fused stream + collide over every cell (eq. LbUpdateScheme, sec. 2.1, with
-//                the collision of sec. 2.2) for the pull, AA, Esoteric-Pull and
+//                the collision of sec. 2.2) for the pull, push, AA, Esoteric-Pull and
 //                Esoteric-Twist patterns (sec. 4.4)
 // init_kernel    zero-centred equilibrium initialisation in FP64 (sec. 2.4)
 // export_kernel / import_kernel   canonical df(t) <-> storage layout
@@ -14,6 +14,9 @@
 // coordinates (integer selects only).  Stores are non-temporal: every population written in
 // a sweep is read again only in the next sweep, after the whole 2 Q sizeof(ST) ncells bytes
 // have streamed through the caches.
+//
+// Push (two buffers): the state between steps is the natural layout (f_i(x) at x, slot i); a
+// step reads the cell's own slots and writes f*_i to x + xi in the other buffer.
 //
 // In-place patterns (one buffer; each step every cell reads and writes the same locations, so
 // the sweep is race-free).  Directions come in opposite pairs (i odd, opp(i) = i + 1).
@@ -213,6 +216,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     if constexpr (PAT == PULL) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+    } else if constexpr (PAT == PUSH) {
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
     } else if constexpr (PAT == AA_EVEN) {
       g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1)));
     } else if constexpr (PAT == AA_ODD) {
@@ -256,6 +261,8 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     const ST v = ST(g[L::gidx(i)]);
     if constexpr (PAT == PULL) {
       stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
+    } else if constexpr (PAT == PUSH) {
+      stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1), nb.lane(cx, cy, +1), v);
     } else if constexpr (PAT == AA_EVEN) {
       stp(a.dst, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), v);
     } else if constexpr (PAT == AA_ODD) {

@@ -42,7 +42,8 @@ int resolve_layout(const lbm_params *p) {
   if (p->layout == LBM_LAYOUT_PLANES || p->layout == LBM_LAYOUT_ROWS) return p->layout;
   // measured: rows for every storage with pull streaming and for F32/F16 with AA; F64 with AA
   // streams faster from planes
-  return (p->storage == LBM_STORE_F64 && p->streaming != LBM_STREAM_PULL) ? LBM_LAYOUT_PLANES : LBM_LAYOUT_ROWS;
+  const bool in_place = p->streaming != LBM_STREAM_PULL && p->streaming != LBM_STREAM_PUSH;
+  return (p->storage == LBM_STORE_F64 && in_place) ? LBM_LAYOUT_PLANES : LBM_LAYOUT_ROWS;
 }
 
 // element strides of population i, z and y (x has stride 1) and elements per buffer
@@ -339,7 +340,7 @@ lbm_status validate(const lbm_params *p) {
     return fail(LBM_EINVAL, "equilibrium out of range");
   if (p->eq_form < LBM_EQFORM_DEFAULT || p->eq_form > LBM_EQFORM_DELTA) return fail(LBM_EINVAL, "eq_form out of range");
   if (p->storage < LBM_STORE_F64 || p->storage > LBM_STORE_F16) return fail(LBM_EINVAL, "storage out of range");
-  if (p->streaming < LBM_STREAM_PULL || p->streaming > LBM_STREAM_ESOTERIC_TWIST)
+  if (p->streaming < LBM_STREAM_PULL || p->streaming > LBM_STREAM_PUSH)
     return fail(LBM_EINVAL, "streaming out of range");
   if (p->nx < 1 || p->ny < 1 || p->nz < 1) return fail(LBM_EINVAL, "dims must be >= 1");
   const int q = stencil_q(p->stencil);
@@ -463,7 +464,7 @@ extern "C" lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes) {
   const lbm_status s = validate(p);
   if (s != LBM_OK) return s;
   if (!bytes) return fail(LBM_EINVAL, "bytes is NULL");
-  const size_t nbuf = p->streaming == LBM_STREAM_PULL ? 2 : 1;
+  const size_t nbuf = (p->streaming == LBM_STREAM_PULL || p->streaming == LBM_STREAM_PUSH) ? 2 : 1;
   uint64_t ps, zs, ys, elems;
   storage_strides(p, &ps, &zs, &ys, &elems);
   *bytes = nbuf * size_t(elems) * storage_bytes(p->storage);

@@ -288,10 +288,16 @@ static hipError_t launch_sweep(const lbm_ctx *c, const void *fn, const void *src
   }
 }
 
+// pull and push alternate between two buffers; the other patterns run in place in one
+static bool two_buffers(const lbm_ctx *c) {
+  return c->pattern == LBM_STREAM_PULL || c->pattern == LBM_STREAM_PUSH;
+}
+
 // sweep kernel pattern of the step that starts at time t, and the layout of df(t)
 static int step_pattern(const lbm_ctx *c, int64_t t) {
   const bool even = t % 2 == 0;
   switch (c->pattern) {
+    case LBM_STREAM_PUSH: return PUSH;
     case LBM_STREAM_AA: return even ? AA_EVEN : AA_ODD;
     case LBM_STREAM_ESOTERIC_PULL: return even ? ESO_EVEN : ESO_ODD;
     case LBM_STREAM_ESOTERIC_TWIST: return even ? TW_EVEN : TW_ODD;
@@ -301,6 +307,7 @@ static int step_pattern(const lbm_ctx *c, int64_t t) {
 static int gather_mode_at(const lbm_ctx *c, int64_t t) {
   const bool even = t % 2 == 0;
   switch (c->pattern) {
+    case LBM_STREAM_PUSH: return G_NATURAL;
     case LBM_STREAM_AA: return even ? G_NATURAL : G_AA_ODD;
     case LBM_STREAM_ESOTERIC_PULL: return even ? G_ESO_EVEN : G_ESO_ODD;
     case LBM_STREAM_ESOTERIC_TWIST: return even ? G_TW_EVEN : G_TW_ODD;
@@ -316,7 +323,7 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
   const int pat = step_pattern(c, c->t);
   const void *src;
   void *dst;
-  if (c->pattern == LBM_STREAM_PULL) {
+  if (two_buffers(c)) {
     src = c->buf[c->cur];
     dst = c->buf[c->cur ^ 1];
   } else {
@@ -341,13 +348,13 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     if (!fn) return fail(LBM_EUNSUPPORTED, "no sweep kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, vec), "sweep launch");
   }
-  if (c->pattern == LBM_STREAM_PULL) c->cur ^= 1;
+  if (two_buffers(c)) c->cur ^= 1;
   c->t += 1;
   return LBM_OK;
 }
 
 static int state_gather_mode(const lbm_ctx *c) { return gather_mode_at(c, c->t); }
-static void *state_buffer(const lbm_ctx *c) { return c->pattern == LBM_STREAM_PULL ? c->buf[c->cur] : c->buf[0]; }
+static void *state_buffer(const lbm_ctx *c) { return two_buffers(c) ? c->buf[c->cur] : c->buf[0]; }
 
 static FieldArgs field_args(const lbm_ctx *c, void *buf, int fbx, int fby) {
   FieldArgs a;
@@ -441,7 +448,7 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
     return s;
   }
   c->reg = c->R.regularized;
-  c->nbuf = c->pattern == LBM_STREAM_PULL ? 2 : 1;
+  c->nbuf = two_buffers(c) ? 2 : 1;
   {
     uint64_t ps, zs, ys, elems;
     storage_strides(p, &ps, &zs, &ys, &elems);
@@ -542,7 +549,7 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const 
 namespace lbm {
 // the cached hipGraph that replays n sweeps from the current buffer parity (recorded once)
 static lbm_status graph_for(lbm_ctx *c, int64_t n, hipGraphExec_t *out) {
-  const int parity = c->pattern == LBM_STREAM_PULL ? c->cur : int(c->t % 2);
+  const int parity = two_buffers(c) ? c->cur : int(c->t % 2);
   auto key = std::make_pair(n, parity);
   auto it = c->gcache.find(key);
   if (it == c->gcache.end()) {
@@ -590,7 +597,7 @@ extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
   lbm_status s = graph_for(c, n, &ex);
   if (s != LBM_OK) return s;
   HIPCHECK(hipGraphLaunch(ex, c->stream), "graph launch");
-  if (c->pattern == LBM_STREAM_PULL) c->cur ^= int(n & 1);
+  if (two_buffers(c)) c->cur ^= int(n & 1);
   c->t += n;
   return LBM_OK;
 }
@@ -757,7 +764,7 @@ extern "C" int64_t lbm_time(const lbm_ctx *c) { return c ? c->t : -1; }
 extern "C" lbm_status lbm_set_time(lbm_ctx *c, int64_t t) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   if (t < 0) return fail(LBM_EINVAL, "t must be >= 0");
-  if (c->pattern != LBM_STREAM_PULL && (t % 2) != (c->t % 2)) {
+  if (!two_buffers(c) && (t % 2) != (c->t % 2)) {
     // odd and even times use different layouts: move the state pair by pair (slots i and
     // opp(i) only exchange with each other) from the old layout to the new one
     const size_t n = c->ncells;
@@ -949,10 +956,10 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
           if (cby > 1 && cby / 2 >= c->ny) continue;
           cand.push_back({cbx, cby, cs, cv});
         }
-  // the sweep must leave the state unchanged: pull writes only the other buffer; the in-place
-  // patterns run on a copy of the buffer that is restored afterwards
+  // the sweep must leave the state unchanged: pull and push write only the other buffer; the
+  // in-place patterns run on a copy of the buffer that is restored afterwards
   void *saved = nullptr;
-  if (c->pattern != LBM_STREAM_PULL) {
+  if (!two_buffers(c)) {
     hipError_t e = hipMalloc(&saved, c->buf_bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();

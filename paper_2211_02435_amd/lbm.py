@@ -19,7 +19,7 @@ SPACES = {"raw": 0, "central": 1, "cumulant": 2, "srt": 3}
 EQUILIBRIA = {"maxwellian": 0, "swe": 1, "swe_maxwellian": 2}
 EQ_FORMS = {"default": 0, "absolute": 1, "delta": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
-STREAMING = {"pull": 0, "aa": 1, "esoteric": 2, "twist": 3}
+STREAMING = {"pull": 0, "aa": 1, "esoteric": 2, "twist": 3, "push": 4}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
 FORCE_MODELS = {"guo": 0, "he": 1}
@@ -210,7 +210,7 @@ class Lattice:
         self._bufs = []
         if torch_buffers:
             total = lbm_required_bytes(p)
-            nbuf = 2 if streaming == "pull" else 1  # the in-place patterns use one array
+            nbuf = 2 if streaming in ("pull", "push") else 1  # the in-place patterns use one array
             per = total // nbuf
             for k in range(nbuf):
                 t = torch.empty(per, dtype=torch.uint8, device="cuda")

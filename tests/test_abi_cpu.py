@@ -91,6 +91,7 @@ def test_valid_parameter_sets():
     (dict(space="raw", arithmetic="literal", streaming="aa"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="esoteric"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="twist"), lbm.LBM_EUNSUPPORTED),
+    (dict(space="raw", arithmetic="literal", streaming="push"), lbm.LBM_EUNSUPPORTED),
     (dict(space="cumulant", arithmetic="literal", eq_form="delta"), lbm.LBM_EUNSUPPORTED),
 ])
 def test_invalid_parameter_sets(kw, code):
@@ -107,8 +108,11 @@ def test_layout_enum_checked_and_large_boxes_accepted():
     p.layout = 7
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
     p = _p()
-    p.streaming = 4
+    p.streaming = 5
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
+    # push keeps two buffers like pull
+    assert lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f32", streaming="push")) == \
+        lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f32", streaming="pull"))
     # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
     assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
 
@@ -144,7 +148,7 @@ def test_d3q15_parameter_sets():
     om = O.regularized_rates("D3Q15", 1.6)
     srt = np.r_[np.zeros(4), np.full(11, 1.6)]
     for store in ("f64", "f32", "f16"):
-        for stream in ("pull", "aa", "esoteric", "twist"):
+        for stream in ("pull", "push", "aa", "esoteric", "twist"):
             for sp, w in (("raw", om), ("srt", srt), ("central", om), ("cumulant", om)):
                 p = _p(stencil="D3Q15", space=sp, omegas=w, storage=store, streaming=stream)
                 assert lbm.lbm_validate(p) == 0, (sp, store, stream, lbm.last_error())
@@ -165,7 +169,7 @@ def test_weighted_orthogonal_basis_parameter_sets():
     for st in ("D2Q9", "D3Q19", "D3Q27"):
         om = O.regularized_rates(st, 1.6)
         for store in ("f64", "f32", "f16"):
-            for stream in ("pull", "aa", "esoteric", "twist"):
+            for stream in ("pull", "push", "aa", "esoteric", "twist"):
                 p = _p(stencil=st, space="raw", omegas=om, storage=store, streaming=stream,
                        basis="weighted_orthogonal")
                 assert lbm.lbm_validate(p) == 0, (st, store, stream, lbm.last_error())

@@ -49,7 +49,7 @@ def _noisy_state(m, dims=RAGGED3, seed=11):
 
 @pytest.mark.parametrize("space,kind", [("raw", "reg"), ("raw", "gen"), ("srt", "gen"), ("central", "reg"),
                                         ("central", "gen"), ("cumulant", "reg"), ("cumulant", "gen")])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
 def test_d3q15_sweep_fp64_matches_oracle(space, kind, streaming, layout):
     om = _rates(space, kind)
@@ -91,7 +91,7 @@ def test_d3q15_init_and_macroscopic_match_oracle(space):
     assert np.abs(rg - ro).max() <= 1e-15 and np.abs(ug - uo).max() <= 1e-15
 
 
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("n", [1, 2, 5])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
 def test_d3q15_streaming_index_maps_bit_exact(streaming, n, layout):

@@ -17,7 +17,7 @@ from paper_2211_02435_amd import lbm
 
 pytestmark = pytest.mark.gpu
 
-STREAMING = ["pull", "aa", "esoteric", "twist"]
+STREAMING = ["pull", "push", "aa", "esoteric", "twist"]
 
 
 def _state(m, dims, seed=3):

@@ -34,7 +34,7 @@ def _rates(stencil, space):
 
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("space", ["raw", "central", "cumulant", "srt"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("model", ["guo", "he"])
 def test_forced_sweep_fp64_matches_oracle(stencil, space, streaming, model):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3

@@ -43,7 +43,7 @@ def _noisy_state(m, dims, seed=11, noise=2e-4):
 
 
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_srt_sweep_matches_oracle(stencil, streaming, storage):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3

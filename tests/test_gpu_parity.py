@@ -46,7 +46,7 @@ def _lattice(stencil, space, om, dims, **kw):
 @pytest.mark.parametrize("stencil,space", [("D2Q9", "raw"), ("D2Q9", "central"), ("D2Q9", "cumulant"),
                                            ("D3Q19", "raw"), ("D3Q19", "central"), ("D3Q19", "cumulant"),
                                            ("D3Q27", "raw"), ("D3Q27", "central"), ("D3Q27", "cumulant")])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 def test_init_equilibrium_matches_oracle(stencil, space, streaming):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     om = _rates(stencil, "reg")
@@ -132,7 +132,7 @@ def test_config_d2q9_central_64_taylor_green():
 
 # ------------------------------------------------------------------------------------------
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 @pytest.mark.parametrize("n", [1, 2, 5])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
 def test_streaming_index_maps_bit_exact(stencil, streaming, n, layout):
@@ -156,13 +156,13 @@ def test_streaming_index_maps_bit_exact(stencil, streaming, n, layout):
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("n", [3, 4])
 def test_aa_equals_pull_in_both_layouts(storage, n):
-    """Pull, AA and Esoteric Pull, planes and rows: six kernels sharing one collision,
-    bit-equal results."""
+    """Pull, push, AA, Esoteric Pull and Esoteric Twist, planes and rows: ten kernels sharing
+    one collision, bit-equal results."""
     dims = RAGGED3
     om = _rates("D3Q27", "reg")
     rho, u = W.tgv3d_fields(*dims, u0=0.05, period=16)
     outs = []
-    for streaming in ("pull", "aa", "esoteric", "twist"):
+    for streaming in ("pull", "push", "aa", "esoteric", "twist"):
         for layout in ("planes", "rows"):
             lat = _lattice("D3Q27", "cumulant", om, dims, storage=storage, streaming=streaming, layout=layout)
             lat.lbm_init_equilibrium(rho, u)
@@ -172,7 +172,7 @@ def test_aa_equals_pull_in_both_layouts(storage, n):
         np.testing.assert_array_equal(outs[0], o)
 
 
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 def test_graph_equals_host_loop_and_checkpoint(streaming):
     dims = RAGGED3
     om = _rates("D3Q27", "gen", seed=9)
@@ -385,7 +385,7 @@ def test_mfma_ablation_close_to_chimera(storage, tol):
 
 
 @pytest.mark.parametrize("space", ["raw", "central", "cumulant"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 def test_absolute_storage_fp64_matches_oracle(space, streaming):
     """Absolute storage (f = df + w in the buffers, eq. MrtUpdateGeneral's storage format):
     FP64 populations after 5 steps against the oracle."""

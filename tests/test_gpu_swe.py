@@ -35,7 +35,7 @@ def _state(m, seed=3):
 
 @pytest.mark.parametrize("space", ["central", "cumulant"])
 @pytest.mark.parametrize("kind", ["reg", "gen"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 def test_swe_maxwellian_fp64_matches_oracle(space, kind, streaming):
     if kind == "reg":
         om = O.regularized_rates("D2Q9", 0.7)

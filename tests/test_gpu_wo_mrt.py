@@ -5,7 +5,7 @@ The WO polynomials mix orders, so the relaxation carries the deviations of order
 orders 4, 5 and 6 (cross-order blocks applied beside the per-order ones).
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 4 steps from a non-equilibrium state (general
-and regularized rates, pull / AA / Esoteric Pull / Esoteric Twist); with every rate 1 the WO and
+and regularized rates, pull / push / AA / Esoteric Pull / Esoteric Twist); with every rate 1 the WO and
 graded runs agree bit for bit (same kernel, no cross term); the FP32 run stays within 1.5e-8 of
 the oracle (two FP32 ulps per step at |df| ~ 0.02 over 4 steps).
 """
@@ -42,7 +42,7 @@ def _noisy_state(m, dims, seed=11):
 
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("kind", ["reg", "gen"])
-@pytest.mark.parametrize("streaming", ["pull", "aa", "esoteric", "twist"])
+@pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
 def test_wo_mrt_fp64_matches_oracle(stencil, kind, streaming):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     om = _rates(stencil, kind)
