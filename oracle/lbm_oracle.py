@@ -11,9 +11,11 @@ tests/test_oracle_*.py check it against something other than itself):
 
   Stencil / weights          sec. 2.1 (D2Q9/D3Q15/D3Q19/D3Q27, xi_0 = 0)
         pin: w == M^-1 m0 (sec. 2.4, background equals the weights), isotropy sums
-  weighted_orthogonal_matrix WO-MRT basis (Table 1, sec. 2.3.1): Gram-Schmidt under the weights
-        pin: orthogonality by brute force, D2Q9 / D3Q27 Hermite product forms, unit-rate
-        basis independence, Taylor-Green viscosity
+  weighted_orthogonal_matrix WO-MRT / O-MRT bases (sec. 2.3.1): Gram-Schmidt under the weights
+        or the plain sum
+        pin: orthogonality by brute force, D2Q9 / D3Q27 Hermite product forms (WO), the
+        Lallemand-Luo D2Q9 polynomials (O), unit-rate basis independence, Taylor-Green
+        viscosity
   moment_matrix              eq. DiscreteRawMomentsDef (sec. 2.3.1)
         pin: closed-form 1-D factorisation, w == M^-1 m0, textbook 2nd-order equilibrium
   central_matrix             eq. DiscreteRawMomentsDef for central moments (sec. 2.3.2)
@@ -182,12 +184,15 @@ class Stencil:
 
 
 @lru_cache(maxsize=None)
-def weighted_orthogonal_matrix(st):
-    """Weighted-orthogonal raw-moment basis (the WO-MRT family of Table 1, sec. 2.3.1):
-    Gram-Schmidt of the graded basis, in its order, under <a, b> = sum_i w_i a(xi_i) b(xi_i).
-    Rows of the returned matrix are the new polynomials' monomial coefficients (columns as
-    st.exps); each is its graded counterpart minus a combination of the earlier ones."""
-    G = (st.M * st.w[None, :]) @ st.M.T  # <monomial_j, monomial_l>_w
+def weighted_orthogonal_matrix(st, weighted=True):
+    """Orthogonal raw-moment bases (sec. 2.3.1 and the operation-count discussion): WO-MRT,
+    the Gram-Schmidt of the graded basis, in its order, under
+    <a, b> = sum_i w_i a(xi_i) b(xi_i); with weighted=False the plain sum over the velocities
+    (O-MRT).  Rows of the returned matrix are the new polynomials' monomial coefficients
+    (columns as st.exps); each is its graded counterpart minus a combination of the earlier
+    ones."""
+    wts = st.w if weighted else np.ones(st.q)
+    G = (st.M * wts[None, :]) @ st.M.T  # <monomial_j, monomial_l>
     rows = []
     for k in range(st.q):
         p = st.P[k].copy()
@@ -431,11 +436,11 @@ class Method:
         self.st = stencil(stencil_name)
         # polynomial basis of the raw-moment relaxation: the graded one, or its
         # weighted-orthogonal counterpart (WO-MRT)
-        assert basis in ("graded", "weighted_orthogonal")
+        assert basis in ("graded", "weighted_orthogonal", "orthogonal")
         self.basis = basis
-        if basis == "weighted_orthogonal":
+        if basis != "graded":
             assert space == "raw" and stencil_name != "D3Q15"
-            self.P = weighted_orthogonal_matrix(self.st)
+            self.P = weighted_orthogonal_matrix(self.st, weighted=basis == "weighted_orthogonal")
         else:
             self.P = self.st.P
         self.space = space

@@ -723,3 +723,44 @@ def test_taylor_green_decay_rate_wo_mrt():
     t = np.arange(0, steps + 1, every)
     rate = -np.polyfit(t[2:], np.log(amps[2:]), 1)[0]
     assert abs(rate / (2 * nu * k * k) - 1) < 5e-3
+
+
+def test_o_mrt_basis_is_lallemand_luo_on_d2q9():
+    """Without weights (O-MRT) the Gram-Schmidt of the graded D2Q9 basis gives the classical
+    polynomials of Lallemand and Luo: energy 3(x^2 + y^2) - 4, energy flux 3 x y^2 - 2 x and
+    3 x^2 y - 2 y, and 9 x^2 y^2 - 6 (x^2 + y^2) + 4 (each divided by its leading coefficient),
+    mutually orthogonal under the plain sum over the nine velocities."""
+    st = O.stencil("D2Q9")
+    Po = O.weighted_orthogonal_matrix(st, weighted=False)
+    names = O.BASIS_NAMES["D2Q9"]
+    want = {
+        "x2+y2": [(1, (2, 0, 0)), (1, (0, 2, 0)), (-4 / 3, (0, 0, 0))],
+        "xy2": [(1, (1, 2, 0)), (-2 / 3, (1, 0, 0))],
+        "x2y": [(1, (2, 1, 0)), (-2 / 3, (0, 1, 0))],
+        "x2y2": [(1, (2, 2, 0)), (-2 / 3, (2, 0, 0)), (-2 / 3, (0, 2, 0)), (4 / 9, (0, 0, 0))],
+    }
+    for nm, terms in want.items():
+        np.testing.assert_allclose(Po[names.index(nm)], _coeffs(st, terms), rtol=0, atol=1e-15, err_msg=nm)
+    v = _poly_values(st, Po)
+    off = v @ v.T - np.diag(np.diag(v @ v.T))
+    assert np.abs(off).max() < 1e-14
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D3Q19", "D3Q27"])
+def test_o_mrt_collision_invariants(name):
+    """O-MRT: unit rates give the graded result, regularized rates keep mass, momentum and the
+    equilibrium, and the three forms agree."""
+    st = O.stencil(name)
+    ones = np.ones(st.q)
+    g1, o1 = O.Method(name, "raw", ones), O.Method(name, "raw", ones, basis="orthogonal")
+    df = _state(g1)
+    np.testing.assert_allclose(O.collide_cells(o1, df, "delta"), O.collide_cells(g1, df, "delta"),
+                               rtol=0, atol=1e-15)
+    o = O.Method(name, "raw", O.regularized_rates(name, 1.7, omega_bulk=1.3), basis="orthogonal")
+    b = O.collide_cells(o, df, "delta")
+    xi = st.xi.astype(float)
+    np.testing.assert_allclose(b.sum(axis=1), df.sum(axis=1), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(b @ xi, df @ xi, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(O.collide_cells(o, df + o.f0, "absolute") - o.f0, b, rtol=0, atol=1e-14)
+    eq = _state(o, noise=0.0)
+    np.testing.assert_allclose(O.collide_cells(o, eq, "delta"), eq, rtol=0, atol=4e-15)
