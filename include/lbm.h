@@ -149,10 +149,11 @@ typedef enum { LBM_FORCE_GUO = 0, LBM_FORCE_HE = 1 } lbm_force_model;
  * Gram-Schmidt orthogonalisation of the graded basis, in its order, under the inner product
  * <a, b> = sum_i w_i a(xi_i) b(xi_i); omegas[k] is the rate of the k-th orthogonalised
  * polynomial.  Its polynomials mix orders, so the relaxation couples a moment to lower orders
- * of the same parity.  WEIGHTED_ORTHOGONAL needs the raw-moment space, the Maxwellian
- * equilibrium, DEVIATION arithmetic, no body force and D2Q9, D3Q19 or D3Q27
- * (LBM_EUNSUPPORTED otherwise); with every rate equal to 1 it equals GRADED. */
-typedef enum { LBM_BASIS_GRADED = 0, LBM_BASIS_WEIGHTED_ORTHOGONAL = 1 } lbm_basis;
+ * of the same parity.  ORTHOGONAL (O-MRT): the same with the plain sum over the velocities
+ * (on D2Q9 the polynomials of Lallemand and Luo).  The orthogonal bases need the raw-moment
+ * space, the Maxwellian equilibrium, DEVIATION arithmetic, no body force and D2Q9, D3Q19 or
+ * D3Q27 (LBM_EUNSUPPORTED otherwise); with every rate equal to 1 they equal GRADED. */
+typedef enum { LBM_BASIS_GRADED = 0, LBM_BASIS_WEIGHTED_ORTHOGONAL = 1, LBM_BASIS_ORTHOGONAL = 2 } lbm_basis;
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,

@@ -1,6 +1,7 @@
 // Host-only part of the library: parameter validation and the relaxation matrix.
 //
 // Pure host code (no HIP runtime calls), so the CPU test suite can exercise it without a GPU.
+#include <algorithm>
 #include <array>
 #include <cmath>
 #include <cstdlib>
@@ -202,12 +203,13 @@ static void host_lattice(int s, std::vector<std::array<int, 3>> *xi, std::vector
 static double ipow(int v, int e) { return e == 0 ? 1.0 : (e % 2 ? double(v) : double(v * v)); }
 
 // rows of P (monomial coefficients over the present monomials `cols`) orthogonalised in order
-// under <a, b> = sum_i w_i a(xi_i) b(xi_i)
-static void weighted_gram_schmidt(int s, const std::vector<int> &cols, std::vector<double> &P) {
+// under <a, b> = sum_i w_i a(xi_i) b(xi_i), or the plain sum over the velocities (weighted false)
+static void weighted_gram_schmidt(int s, const std::vector<int> &cols, std::vector<double> &P, bool weighted) {
   const int q = int(cols.size());
   std::vector<std::array<int, 3>> xi;
   std::vector<double> w;
   host_lattice(s, &xi, &w);
+  if (!weighted) std::fill(w.begin(), w.end(), 1.0);
   // G[j][l] = <monomial_j, monomial_l>
   std::vector<double> G(size_t(q) * q, 0.0);
   for (int j = 0; j < q; ++j)
@@ -253,7 +255,8 @@ lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *
   std::vector<double> P(size_t(q) * q, 0.0);
   for (int r = 0; r < q; ++r)
     for (const Term &t : B[r]) P[size_t(r) * q + colof[t.a + 3 * t.b + 9 * t.z]] += t.c;
-  if (basis == LBM_BASIS_WEIGHTED_ORTHOGONAL) weighted_gram_schmidt(s, cols, P);
+  if (basis == LBM_BASIS_WEIGHTED_ORTHOGONAL || basis == LBM_BASIS_ORTHOGONAL)
+    weighted_gram_schmidt(s, cols, P, basis == LBM_BASIS_WEIGHTED_ORTHOGONAL);
   std::vector<double> Pinv = P;
   if (!invert(Pinv, q)) return fail(LBM_EINVAL, "internal: singular basis");
   // A = P^-1 S P with the conserved rows (1, x, y, z) at rate 0
@@ -364,17 +367,16 @@ lbm_status validate(const lbm_params *p) {
   if (p->space == LBM_SPACE_CUMULANT && p->eq_form == LBM_EQFORM_DELTA)
     return fail(LBM_EUNSUPPORTED, "the cumulant transform is nonlinear: no delta-equilibrium in cumulant space");
   if (p->stencil == LBM_D2Q9 && p->nz != 1) return fail(LBM_EUNSUPPORTED, "D2Q9 requires nz == 1");
-  if (p->basis != LBM_BASIS_GRADED && p->basis != LBM_BASIS_WEIGHTED_ORTHOGONAL)
-    return fail(LBM_EINVAL, "basis out of range");
-  if (p->basis == LBM_BASIS_WEIGHTED_ORTHOGONAL) {
-    if (p->space != LBM_SPACE_RAW) return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis is a raw-moment basis");
+  if (p->basis < LBM_BASIS_GRADED || p->basis > LBM_BASIS_ORTHOGONAL) return fail(LBM_EINVAL, "basis out of range");
+  if (p->basis != LBM_BASIS_GRADED) {
+    if (p->space != LBM_SPACE_RAW) return fail(LBM_EUNSUPPORTED, "the orthogonal bases are raw-moment bases");
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
-      return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis runs with the Maxwellian equilibrium");
+      return fail(LBM_EUNSUPPORTED, "the orthogonal bases run with the Maxwellian equilibrium");
     if (p->arithmetic != LBM_ARITH_DEVIATION)
-      return fail(LBM_EUNSUPPORTED, "the weighted-orthogonal basis runs with the deviation arithmetic");
-    if (p->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "no weighted-orthogonal basis for D3Q15");
+      return fail(LBM_EUNSUPPORTED, "the orthogonal bases run with the deviation arithmetic");
+    if (p->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "no orthogonal basis for D3Q15");
     if (p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0)
-      return fail(LBM_EUNSUPPORTED, "no body force with the weighted-orthogonal basis");
+      return fail(LBM_EUNSUPPORTED, "no body force with the orthogonal bases");
   }
   if (p->stencil == LBM_D3Q15) {
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)

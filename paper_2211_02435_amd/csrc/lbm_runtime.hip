@@ -633,7 +633,7 @@ extern "C" lbm_status lbm_set_force_field(lbm_ctx *c, const double *F) {
   if (c->literal) return fail(LBM_EUNSUPPORTED, "the body force runs with the deviation arithmetic");
   if (c->transform == LBM_TRANSFORM_DENSE_MFMA) return fail(LBM_EUNSUPPORTED, "no body force in the MFMA ablation");
   if (c->R.cross || c->p.basis != LBM_BASIS_GRADED)
-    return fail(LBM_EUNSUPPORTED, "no body force with the weighted-orthogonal basis");
+    return fail(LBM_EUNSUPPORTED, "no body force with the orthogonal bases");
   const size_t n = 3 * size_t(c->ncells);
   std::vector<double> h(n);
   if (is_device_ptr(F)) HIPCHECK(hipMemcpy(h.data(), F, n * sizeof(double), hipMemcpyDeviceToHost), "force copy");

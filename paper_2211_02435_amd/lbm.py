@@ -23,7 +23,7 @@ STREAMING = {"pull": 0, "aa": 1, "esoteric": 2, "twist": 3, "push": 4}
 LAYOUTS = {"auto": 0, "planes": 1, "rows": 2}
 ARITHMETIC = {"deviation": 0, "literal": 1}
 FORCE_MODELS = {"guo": 0, "he": 1}
-BASES = {"graded": 0, "weighted_orthogonal": 1}
+BASES = {"graded": 0, "weighted_orthogonal": 1, "orthogonal": 2}
 Q = {"D2Q9": 9, "D3Q19": 19, "D3Q27": 27, "D3Q15": 15}
 # order of every polynomial of the bases documented in lbm.h (one rate per entry of omegas)
 BASIS_ORDERS = {

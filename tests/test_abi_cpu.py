@@ -164,15 +164,15 @@ def test_d3q15_parameter_sets():
 
 
 def test_weighted_orthogonal_basis_parameter_sets():
-    """The weighted-orthogonal basis is accepted for raw-moment MRT on D2Q9, D3Q19 and D3Q27
+    """The orthogonal bases (WO, O) are accepted for raw-moment MRT on D2Q9, D3Q19 and D3Q27
     (any storage and streaming pattern) and rejected elsewhere."""
     for st in ("D2Q9", "D3Q19", "D3Q27"):
         om = O.regularized_rates(st, 1.6)
         for store in ("f64", "f32", "f16"):
             for stream in ("pull", "push", "aa", "esoteric", "twist"):
-                p = _p(stencil=st, space="raw", omegas=om, storage=store, streaming=stream,
-                       basis="weighted_orthogonal")
-                assert lbm.lbm_validate(p) == 0, (st, store, stream, lbm.last_error())
+                for basis in ("weighted_orthogonal", "orthogonal"):
+                    p = _p(stencil=st, space="raw", omegas=om, storage=store, streaming=stream, basis=basis)
+                    assert lbm.lbm_validate(p) == 0, (st, store, stream, basis, lbm.last_error())
     om = O.regularized_rates("D3Q27", 1.6)
     for kw in (dict(space="central"), dict(space="cumulant"), dict(space="srt", omegas=np.r_[np.zeros(4), np.full(23, 1.6)]),
                dict(space="raw", arithmetic="literal"), dict(space="raw", force=(1e-5, 0, 0)),
@@ -182,8 +182,9 @@ def test_weighted_orthogonal_basis_parameter_sets():
         kw.setdefault("omegas", om)
         assert lbm.lbm_validate(_p(basis="weighted_orthogonal", **kw)) == lbm.LBM_EUNSUPPORTED, kw
         assert lbm.last_error() != ""
+        assert lbm.lbm_validate(_p(basis="orthogonal", **kw)) == lbm.LBM_EUNSUPPORTED, kw
     p = _p(space="raw", omegas=om)
-    p.basis = 2
+    p.basis = 3
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL
 
 

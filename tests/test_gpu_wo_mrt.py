@@ -1,7 +1,7 @@
-"""Raw-moment MRT in the weighted-orthogonal basis (WO-MRT, Table 1, sec. 2.3.1) on the GPU
-against the FP64 oracle, through the C ABI.
+"""Raw-moment MRT in the weighted-orthogonal (WO-MRT) and the non-weighted orthogonal (O-MRT)
+bases (sec. 2.3.1) on the GPU against the FP64 oracle, through the C ABI.
 
-The WO polynomials mix orders, so the relaxation carries the deviations of orders 2 and 3 into
+The orthogonal polynomials mix orders, so the relaxation carries the deviations of orders 2 and 3 into
 orders 4, 5 and 6 (cross-order blocks applied beside the per-order ones).
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 4 steps from a non-equilibrium state (general
@@ -43,16 +43,17 @@ def _noisy_state(m, dims, seed=11):
 @pytest.mark.parametrize("stencil", ["D2Q9", "D3Q19", "D3Q27"])
 @pytest.mark.parametrize("kind", ["reg", "gen"])
 @pytest.mark.parametrize("streaming", ["pull", "push", "aa", "esoteric", "twist"])
-def test_wo_mrt_fp64_matches_oracle(stencil, kind, streaming):
+@pytest.mark.parametrize("basis", ["weighted_orthogonal", "orthogonal"])
+def test_wo_mrt_fp64_matches_oracle(stencil, kind, streaming, basis):
     dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
     om = _rates(stencil, kind)
-    m = O.Method(stencil, "raw", om, basis="weighted_orthogonal")
+    m = O.Method(stencil, "raw", om, basis=basis)
     df0 = _noisy_state(m, dims)
-    lat = lbm.Lattice(stencil, "raw", om, dims, storage="f64", streaming=streaming, basis="weighted_orthogonal")
+    lat = lbm.Lattice(stencil, "raw", om, dims, storage="f64", streaming=streaming, basis=basis)
     lat.lbm_set_populations(df0)
     lat.lbm_step(4)
     err = np.abs(lat.lbm_get_populations() - O.step(m, df0, 4)).max()
-    print("WO-MRT %s %s %s max|d df| = %.3e" % (stencil, kind, streaming, err))
+    print("%s %s %s %s max|d df| = %.3e" % (basis, stencil, kind, streaming, err))
     assert err <= 1e-13
 
 
