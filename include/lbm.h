@@ -188,8 +188,8 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fill *p with defaults: D3Q27, cumulant, Maxwellian, DEFAULT form, zero-centred, FP32, pull,
- * periodic, 1x1x1, no rates, AUTO layout, DEVIATION arithmetic.  Always succeeds for
- * non-NULL p. */
+ * periodic, 1x1x1, no rates, AUTO layout, DEVIATION arithmetic, no force (Guo's model),
+ * GRADED basis.  Always succeeds for non-NULL p. */
 lbm_status lbm_params_default(lbm_params *p);
 
 /* Validate a parameter set without touching any device (pure host code).
@@ -200,7 +200,9 @@ lbm_status lbm_params_default(lbm_params *p);
  * nz != 1, the shallow-water equilibria on a 3-D stencil, Zhou's in cumulant space, Venturi's
  * outside central and cumulant space, non-periodic
  * axes, SRT with unequal rates (EINVAL) or the shallow-water equilibrium, LITERAL arithmetic
- * outside D2Q9/D3Q27, F64/F32, pull, Maxwellian.
+ * outside D2Q9/D3Q27, F64/F32, pull, Maxwellian, a body force with LITERAL arithmetic or a
+ * shallow-water equilibrium, D3Q15 with another equilibrium or LITERAL arithmetic, and the
+ * orthogonal bases outside their domain (lbm_basis).
  * Absolute storage keeps f = df + w in the buffers (the "absolute" storage format of the
  * paper, used for the round-off plateau study of sec. 5.1).  With DEVIATION arithmetic every
  * sweep subtracts w after loading and adds it back before storing, so only the storage
@@ -208,7 +210,7 @@ lbm_status lbm_params_default(lbm_params *p);
 lbm_status lbm_validate(const lbm_params *p);
 
 /* Bytes of device population storage the parameter set needs in total (both arrays for
- * pull, one for AA).  PLANES: nbuffers * q * plane * sizeof(storage), the plane stride being
+ * pull and push, one for the in-place patterns).  PLANES: nbuffers * q * plane * sizeof(storage), the plane stride being
  * ncells rounded up to 256 bytes plus a padding that staggers the q planes across HBM
  * channels (environment variable LBM_PLANE_PAD_BYTES overrides the padding).  ROWS:
  * nbuffers * nz * ny * q * nxp * sizeof(storage), nxp = nx rounded up to 256 bytes.
