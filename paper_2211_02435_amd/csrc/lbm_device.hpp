@@ -267,13 +267,12 @@ struct Relax {
   T b4[6][6];
   T b5[3][3];
   T b6;
-  // cross-order blocks (weighted-orthogonal raw basis), applied to the pre-relaxation
-  // deviations: orders 2 -> 4, 3 -> 5, 2 -> 6 and 4 -> 6; cross == 0 when all vanish
+  // cross-order blocks (orthogonal raw bases), applied to the pre-relaxation deviations by
+  // the CROSS kernels: orders 2 -> 4, 3 -> 5, 2 -> 6 and 4 -> 6
   T c42[6][6];
   T c53[3][7];
   T c62[6];
   T c64[6];
-  int cross;
 };
 
 // exponent grid indices of each order (3-D); 2-D uses the c = 0 entries
@@ -622,9 +621,13 @@ LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
 // u = (j + F/2) / rho, the first-order non-equilibrium moments are -F/2, and the source
 // moments weighted by (I - P^-1 S P / 2) = (I + B) / 2 are added in the collision space
 // (raw moments, or central moments for the central and cumulant spaces); momentum grows by F.
-template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
+// With CROSS the raw-moment relaxation adds the cross-order blocks of an orthogonal basis
+// (a separate instantiation, so the graded kernels carry none of that arithmetic).
+template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false, bool CROSS = false>
 LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullptr, int fmodel = FORCE_GUO) {
   static_assert(!(FORCE && REG), "the forced collision uses the general kernel");
+  static_assert(!CROSS || (SP == RAW && !REG && !FORCE && S != D3Q15),
+                "the cross-order blocks belong to the unforced general raw-moment kernel");
   constexpr int D = Lat<S>::D;
   constexpr int G = Lat<S>::G;
   constexpr int EX = 1, EY = 3, EZ = 9;
@@ -707,18 +710,14 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   };
 
   if constexpr (SP == RAW) {
-    if constexpr (!REG && S != D3Q15) {
-      if (R.cross) {
-        T x[G];
-        cross_orders<S>(x, v, R);
-        relax<S, false>(v, R);
-        sfor<G>([&](auto E) {
-          constexpr int e = decltype(E)::value;
-          if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 4) v[e] += x[e];
-        });
-      } else {
-        relax<S, false>(v, R);
-      }
+    if constexpr (CROSS) {
+      T x[G];
+      cross_orders<S>(x, v, R);
+      relax<S, false>(v, R);
+      sfor<G>([&](auto E) {
+        constexpr int e = decltype(E)::value;
+        if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 4) v[e] += x[e];
+      });
     } else {
       relax<S, REG>(v, R);
     }
@@ -790,13 +789,13 @@ LBM_HD void collide_srt(T *g, const Relax<T> &R, const T *F = nullptr, int fmode
 // ---------------------------------------------------------------------------------------
 // the collision: g holds df (grid order, missing velocities zero) and receives df*
 // ---------------------------------------------------------------------------------------
-template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false>
+template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false, bool CROSS = false>
 LBM_HD void collide(T *g, const Relax<T> &R, T grav, const T *F = nullptr, int fmodel = FORCE_GUO) {
   if constexpr (SP == SRT) {
     collide_srt<S, T, FORCE>(g, R, F, fmodel);
   } else if constexpr (SP != IDENTITY) {
     chimera_forward<S>(g);
-    collide_moments<S, SP, EQ, REG, T, FORCE>(g, R, grav, F, fmodel);
+    collide_moments<S, SP, EQ, REG, T, FORCE, CROSS>(g, R, grav, F, fmodel);
     chimera_inverse<S>(g);
   }
 }

@@ -202,7 +202,7 @@ struct NbrNat {
 // ---------------------------------------------------------------------------------------
 // fused stream + collide
 // ---------------------------------------------------------------------------------------
-template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT, bool FORCE = false>
+template <int S, int SP, int EQ, bool REG, class ST, class CT, int PAT, bool FORCE = false, bool CROSS = false>
 __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
   using L = Lat<S>;
   const CellPos p = tile_cell_args(a, 1);
@@ -251,7 +251,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
     if constexpr (L::D == 2) F[2] = CT(0);
     collide<S, SP, EQ, REG, CT, true>(g, a.R, a.grav, F, a.force_model);
   } else {
-    collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+    collide<S, SP, EQ, REG, CT, false, CROSS>(g, a.R, a.grav);
   }
   if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
 

@@ -50,6 +50,7 @@ const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_
 const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
 const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
 const void *sweep_force_fn(int s, int store, int sp, int pat) { LBM_TABLE_CALL(sweep_force, sp, pat) }
+const void *sweep_cross_fn(int s, int store, int pat) { LBM_TABLE_CALL(sweep_cross, pat) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -246,7 +247,6 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
     a.R.c62[k] = CT(c->R.c62[k]);
     a.R.c64[k] = CT(c->R.c64[k]);
   }
-  a.R.cross = c->R.cross ? 1 : 0;
   return a;
 }
 
@@ -342,6 +342,11 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     const void *fn = sweep_mfma_fn(c->s, c->store, sp, reg);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no MFMA ablation kernel for this method");
     HIPCHECK(launch_sweep_lds(c, fn, src, dst, mfma_lds_bytes(c)), "sweep launch");
+  } else if (c->R.cross && sp_override < 0) {
+    // an orthogonal raw basis: the general raw kernel with the cross-order blocks
+    const void *fn = sweep_cross_fn(c->s, c->store, pat);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no cross-order kernel for this stencil");
+    HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
   } else {
     const bool vec = c->vec && (pat == PULL || pat == AA_EVEN) && vec_ok(c, c->bx);
     const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);

@@ -14,7 +14,8 @@ each pull-streaming sweep kernel: additions and subtractions, multiplications, f
 multiply-adds (two operations each), reciprocals and the division steps.  Loads, stores,
 address and integer arithmetic are not counted, matching a count of the collision's
 arithmetic.  The scalar sweep is straight-line per cell (one cell per lane), so the static
-count is the per-cell count.
+count is the per-cell count.  The graded-basis kernels are counted; the orthogonal-basis
+variants (which add the cross-order blocks) are left out.
 
   python -m paper_2211_02435_amd.op_count [--storage f32|f64] [--json out.json]
 """
@@ -92,7 +93,8 @@ def demangle(names):
     return r.stdout.splitlines()
 
 
-_SWEEP = re.compile(r"^void lbm::sweep_kernel<(\d+), (\d+), (\d+), (true|false), (\w+), (\w+), (\d+), (true|false)>")
+_SWEEP = re.compile(r"^void lbm::sweep_kernel<(\d+), (\d+), (\d+), (true|false), (\w+), (\w+), (\d+), (true|false)"
+                    r"(?:, (true|false))?>")
 
 
 def sweep_counts(storage="f32", stencils=("D3Q19", "D3Q27"), workdir=None):
@@ -111,8 +113,8 @@ def sweep_counts(storage="f32", stencils=("D3Q19", "D3Q27"), workdir=None):
             m = _SWEEP.match(pretty)
             if not m:
                 continue
-            s, sp, eq, reg, st, ct, pat, force = m.groups()
-            if eq != "0" or pat != "0" or force != "false" or int(sp) == 3:
+            s, sp, eq, reg, st, ct, pat, force, cross = m.groups()
+            if eq != "0" or pat != "0" or force != "false" or int(sp) == 3 or cross == "true":
                 continue
             c = funcs[mangled]
             rows.append(dict(stencil=STENCILS[int(s)], space=SPACES[int(sp)],

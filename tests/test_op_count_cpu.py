@@ -45,7 +45,7 @@ def test_summary_ratios():
 
 
 def test_demangle_matches_sweep_pattern():
-    name = "_ZN3lbm12sweep_kernelILi2ELi2ELi0ELb1EffLi0ELb0EEEvNS_9SweepArgsIT3_T4_EE"
+    name = "_ZN3lbm12sweep_kernelILi2ELi2ELi0ELb1EffLi0ELb0ELb0EEEvNS_9SweepArgsIT3_T4_EE"
     pretty = OC.demangle([name])[0]
     m = OC._SWEEP.match(pretty)
-    assert m and m.groups() == ("2", "2", "0", "true", "float", "float", "0", "false")
+    assert m and m.groups() == ("2", "2", "0", "true", "float", "float", "0", "false", "false")
