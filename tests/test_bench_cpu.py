@@ -1,0 +1,29 @@
+"""Host checks of bench.py that need no GPU: one GPU only, and the traffic record is read
+only for the layout and kernel sources it was measured with."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_traffic_record_matches_layout_and_sources(tmp_path, monkeypatch):
+    sys.path.insert(0, ROOT)
+    import bench
+    from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
+    rec = os.path.join(ROOT, "profiles", "traffic_d3q27_cumulant_512.json")
+    t = json.load(open(rec))
+    if t["kernel_source_sha"] == kernel_source_hash():
+        assert bench.measured_traffic("d3q27_cumulant_512", t["layout"]) == t["bytes_per_launch"]
+    other = "planes" if t["layout"] == "rows" else "rows"
+    assert bench.measured_traffic("d3q27_cumulant_512", other) is None
+    assert bench.measured_traffic("no_such_workload", t["layout"]) is None
