@@ -119,6 +119,7 @@ def measure_batch(lbm, steps, warmup):
     bat = lbm.Batch("D3Q27", "central", dims, rates, storage="f32")
     bat.lbm_batch_init_equilibrium(rho, u)
     del rho, u
+    launch = bat.lbm_batch_autotune()
     bat.lbm_batch_step(warmup)
     bat.lbm_batch_graph_prepare(steps)
     bat.lbm_batch_synchronize()
@@ -132,7 +133,7 @@ def measure_batch(lbm, steps, warmup):
     return {"boxes": len(boxes), "cells": cells, "steps": steps, "graph_steps": steps,
             "mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
             "avg_launch_ms": ms / steps, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
-            "storage": "f32", "space": "central"}
+            "storage": "f32", "space": "central", "launch_threads_swizzle_lds": list(launch)}
 
 
 def cpu_baseline(cfg, n, steps):

@@ -350,6 +350,17 @@ lbm_status lbm_batch_synchronize(lbm_batch *b);
 int64_t lbm_batch_cells(const lbm_batch *b);
 lbm_status lbm_batch_set_graphs(lbm_batch *b, int enable);
 lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms);
+/* Launch shape of the ensemble sweep: `threads` cells per tile (= threads per block, a
+ * multiple of 64 in [64, 512]; default 256), tiles taken in XCD order (swizzle != 0, default)
+ * and `lds_bytes` of dynamic LDS reserved per block (0..65536; caps the resident blocks per
+ * CU).  Results do not depend on it.  Rebuilds the tile table; synchronous.  LBM_EINVAL for
+ * values out of range. */
+lbm_status lbm_batch_set_launch(lbm_batch *b, int threads, int swizzle, int lds_bytes);
+lbm_status lbm_batch_get_launch(const lbm_batch *b, int *threads, int *swizzle, int *lds_bytes);
+/* Times one sweep for every tile size in {128, 256, 512}, both tile orders and the LDS
+ * reserves {0, 16, 24, 32, 40} KiB, and keeps the fastest.  The state and the step counter
+ * are left unchanged (each timed sweep writes only the other buffer).  Synchronous. */
+lbm_status lbm_batch_autotune(lbm_batch *b);
 
 /* --------------------------------------------------------------------------------------
  * Measurement helpers

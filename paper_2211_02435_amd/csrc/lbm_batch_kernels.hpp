@@ -2,8 +2,9 @@
 //
 // Populations of all boxes share one SoA buffer, plane stride ntot = sum of box cells; box b
 // occupies cells [off_b, off_b + ncells_b) of every plane.  Blocks walk a flat tile list:
-// tile k belongs to box tile_box[k] and covers 256-cell chunks of that box in memory order
-// (x fastest), so every block reads and writes contiguous rows whatever the box edge.  Blocks
+// tile k belongs to box tile_box[k] and covers blockDim.x consecutive cells of that box in
+// memory order (x fastest; the tile size is a launch parameter, chosen by the autotuner), so
+// every block reads and writes contiguous rows whatever the box edge.  Blocks
 // take tiles in XCD order (each XCD a contiguous range), so the cache lines that neighbouring
 // tiles share are fetched into one L2.
 #pragma once
@@ -30,15 +31,16 @@ struct BatchArgs {
   int swizzle;               // nonzero: consecutive tiles on one XCD (shared boundary lines in one L2)
 };
 
-constexpr int BATCH_THREADS = 256;
+constexpr int BATCH_THREADS = 256;      // default tile size (cells = threads per block)
+constexpr int BATCH_MAX_THREADS = 512;
 
 template <int S, int SP, int EQ, bool REG, class ST, class CT>
-__global__ void __launch_bounds__(BATCH_THREADS) batch_sweep_kernel(BatchArgs<ST, CT> a) {
+__global__ void __launch_bounds__(BATCH_MAX_THREADS) batch_sweep_kernel(BatchArgs<ST, CT> a) {
   using L = Lat<S>;
   const uint32_t tile = a.swizzle ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t b = a.tile_box[tile];
   const BoxInfo B = a.boxes[b];
-  const uint32_t c = (tile - B.tile0) * BATCH_THREADS + threadIdx.x;
+  const uint32_t c = (tile - B.tile0) * blockDim.x + threadIdx.x;
   if (c >= B.ncells) return;
   const uint32_t nxy = uint32_t(B.nx) * uint32_t(B.ny);
   const int z = int(c / nxy);

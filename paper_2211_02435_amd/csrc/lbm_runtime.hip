@@ -1121,6 +1121,7 @@ struct lbm_batch {
   int nboxes = 0;
   std::vector<BoxInfo> boxes;
   uint32_t ntot = 0, ntiles = 0;
+  uint64_t ntiles_cap = 0;  // capacity of tile_box_d
   BoxInfo *boxes_d = nullptr;
   uint32_t *tile_box_d = nullptr;
   void *relax_d = nullptr;
@@ -1134,6 +1135,8 @@ struct lbm_batch {
   double *staging = nullptr;
   size_t staging_doubles = 0;
   int swz = 1;  // XCD-ordered tiles (LBM_BATCH_SWIZZLE=0 switches it off)
+  int bt = BATCH_THREADS;  // cells per tile = threads per block
+  int lds = 0;             // dynamic LDS reserved per block (caps resident blocks per CU)
 };
 
 namespace lbm {
@@ -1154,7 +1157,7 @@ static lbm_status batch_one_step(lbm_batch *b) {
     a.relax = static_cast<const Relax<CT> *>(b->relax_d);
     a.swizzle = b->swz;
     void *args[] = {&a};
-    return hipLaunchKernel(fn, dim3(b->ntiles), dim3(BATCH_THREADS), args, 0, b->stream);
+    return hipLaunchKernel(fn, dim3(b->ntiles), dim3(b->bt), args, size_t(b->lds), b->stream);
   };
   if (b->store == F64) e = go(std::pair<double, double>());
   else if (b->store == F32) e = go(std::pair<float, float>());
@@ -1163,6 +1166,45 @@ static lbm_status batch_one_step(lbm_batch *b) {
   b->cur ^= 1;
   b->t += 1;
   return LBM_OK;
+}
+
+// tile table for tiles of bt cells: the first tile of every box and the box of every tile
+static lbm_status batch_build_tiles(lbm_batch *b, int bt) {
+  uint64_t tiles = 0;
+  for (auto &B : b->boxes) {
+    B.tile0 = uint32_t(tiles);
+    tiles += (B.ncells + uint32_t(bt) - 1) / uint32_t(bt);
+  }
+  if (tiles >= (uint64_t(1) << 31)) return fail(LBM_EUNSUPPORTED, "too many tiles");
+  std::vector<uint32_t> tb(tiles);
+  for (size_t k = 0; k < b->boxes.size(); ++k) {
+    const uint32_t nt = (b->boxes[k].ncells + uint32_t(bt) - 1) / uint32_t(bt);
+    for (uint32_t j = 0; j < nt; ++j) tb[b->boxes[k].tile0 + j] = uint32_t(k);
+  }
+  if (b->stream) HIPCHECK(hipStreamSynchronize(b->stream), "sync");
+  if (b->tile_box_d && tiles > b->ntiles_cap) {
+    (void)hipFree(b->tile_box_d);
+    b->tile_box_d = nullptr;
+  }
+  if (!b->tile_box_d) {
+    hipError_t e = hipMalloc(&b->tile_box_d, sizeof(uint32_t) * tiles);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LBM_ENOMEM, "tile table allocation failed");
+    }
+    b->ntiles_cap = tiles;
+  }
+  HIPCHECK(hipMemcpy(b->tile_box_d, tb.data(), sizeof(uint32_t) * tiles, hipMemcpyHostToDevice), "tile table copy");
+  HIPCHECK(hipMemcpy(b->boxes_d, b->boxes.data(), sizeof(BoxInfo) * b->boxes.size(), hipMemcpyHostToDevice),
+           "box table copy");
+  b->ntiles = uint32_t(tiles);
+  b->bt = bt;
+  return LBM_OK;
+}
+
+static void batch_clear_graphs(lbm_batch *b) {
+  for (auto &kv : b->gcache) (void)hipGraphExecDestroy(kv.second);
+  b->gcache.clear();
 }
 
 static lbm_status batch_staging(lbm_batch *b, size_t nd) {
@@ -1283,6 +1325,7 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   }
   if ((e = hipMalloc(&b->boxes_d, sizeof(BoxInfo) * nboxes)) != hipSuccess) return bail(e, "box table");
   if ((e = hipMalloc(&b->tile_box_d, sizeof(uint32_t) * b->ntiles)) != hipSuccess) return bail(e, "tile table");
+  b->ntiles_cap = b->ntiles;
   const bool dbl = b->store == F64;
   const size_t rsz = dbl ? sizeof(Relax<double>) : sizeof(Relax<float>);
   if ((e = hipMalloc(&b->relax_d, rsz * nboxes)) != hipSuccess) return bail(e, "relaxation table");
@@ -1481,6 +1524,86 @@ extern "C" lbm_status lbm_batch_set_graphs(lbm_batch *b, int enable) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   b->graphs = enable != 0;
   return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_set_launch(lbm_batch *b, int threads, int swizzle, int lds_bytes) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (threads < 64 || threads > BATCH_MAX_THREADS || threads % 64 != 0)
+    return fail(LBM_EINVAL, "threads must be a multiple of 64 in [64, 512]");
+  if (lds_bytes < 0 || lds_bytes > 65536) return fail(LBM_EINVAL, "lds_bytes must be in [0, 65536]");
+  if (threads != b->bt) {
+    lbm_status s = batch_build_tiles(b, threads);
+    if (s != LBM_OK) return s;
+  }
+  batch_clear_graphs(b);
+  b->swz = swizzle ? 1 : 0;
+  b->lds = lds_bytes;
+  return LBM_OK;
+}
+
+extern "C" lbm_status lbm_batch_get_launch(const lbm_batch *b, int *threads, int *swizzle, int *lds_bytes) {
+  if (!b || !threads || !swizzle || !lds_bytes) return fail(LBM_EINVAL, "NULL argument");
+  *threads = b->bt;
+  *swizzle = b->swz;
+  *lds_bytes = b->lds;
+  return LBM_OK;
+}
+
+// Times one sweep (src -> dst, the state and the step counter untouched) for every tile size,
+// XCD order and LDS reserve, and keeps the fastest.
+extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  const int cur0 = b->cur;
+  const int64_t t0 = b->t;
+  const int bt0 = b->bt, swz0 = b->swz, lds0 = b->lds;
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  HIPCHECK(hipEventCreate(&e1), "event");
+  const int reps = 5;
+  double best = 1e300;
+  int bb[3] = {bt0, swz0, lds0};
+  lbm_status st = LBM_OK;
+  for (int bt : {128, 256, 512}) {
+    st = batch_build_tiles(b, bt);
+    if (st != LBM_OK) break;
+    for (int swz : {0, 1}) {
+      for (int lds : {0, 16384, 24576, 32768, 40960}) {
+        b->swz = swz;
+        b->lds = lds;
+        for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
+          if (r == 1) (void)hipEventRecord(e0, b->stream);
+          b->cur = cur0;
+          b->t = t0;
+          st = batch_one_step(b);
+        }
+        (void)hipEventRecord(e1, b->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (st != LBM_OK) break;
+        if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
+          std::fprintf(stderr, "[lbm batch autotune] threads %d swizzle %d lds %d: %.4f ms/step\n", bt, swz, lds,
+                       ms / reps);
+        if (ms < best) {
+          best = ms;
+          bb[0] = bt;
+          bb[1] = swz;
+          bb[2] = lds;
+        }
+      }
+      if (st != LBM_OK) break;
+    }
+    if (st != LBM_OK) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->cur = cur0;
+  b->t = t0;
+  lbm_status s2 = batch_build_tiles(b, st == LBM_OK ? bb[0] : bt0);
+  b->swz = st == LBM_OK ? bb[1] : swz0;
+  b->lds = st == LBM_OK ? bb[2] : lds0;
+  batch_clear_graphs(b);
+  return st != LBM_OK ? st : s2;
 }
 
 extern "C" lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms) {

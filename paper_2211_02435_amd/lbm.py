@@ -110,6 +110,9 @@ SIGNATURES = {
     "lbm_batch_cells": (c_int64, [c_void_p]),
     "lbm_batch_set_graphs": (c_int, [c_void_p, c_int]),
     "lbm_batch_time_steps": (c_int, [c_void_p, c_int64, POINTER(c_double)]),
+    "lbm_batch_set_launch": (c_int, [c_void_p, c_int, c_int, c_int]),
+    "lbm_batch_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
+    "lbm_batch_autotune": (c_int, [c_void_p]),
     "lbm_copy_bandwidth": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]),
     "lbm_debug_stream_only": (c_int, [c_void_p, c_int64]),
 }
@@ -397,6 +400,18 @@ class Batch:
 
     def lbm_batch_cells(self):
         return int(self.lib.lbm_batch_cells(self.b))
+
+    def lbm_batch_set_launch(self, threads, swizzle=1, lds_bytes=0):
+        check(self.lib.lbm_batch_set_launch(self.b, int(threads), int(swizzle), int(lds_bytes)))
+
+    def lbm_batch_get_launch(self):
+        t, s, l = c_int(), c_int(), c_int()
+        check(self.lib.lbm_batch_get_launch(self.b, ctypes.byref(t), ctypes.byref(s), ctypes.byref(l)))
+        return t.value, s.value, l.value
+
+    def lbm_batch_autotune(self):
+        check(self.lib.lbm_batch_autotune(self.b))
+        return self.lbm_batch_get_launch()
 
     def lbm_batch_set_graphs(self, enable):
         check(self.lib.lbm_batch_set_graphs(self.b, 1 if enable else 0))
