@@ -194,7 +194,9 @@ lbm_status lbm_params_default(lbm_params *p);
 
 /* Validate a parameter set without touching any device (pure host code).
  * LBM_EINVAL for bad enums, dims < 1, n_omegas != q, NULL omegas, non-finite or out-of-range
- * rates, gravity <= 0 with the shallow-water equilibrium.  LBM_EUNSUPPORTED for the
+ * rates, gravity <= 0 with the shallow-water equilibrium; LBM_EUNSUPPORTED for boxes of 2^32
+ * cells or more (32-bit natural cell indices) or with a z-plane of population storage of
+ * 4 GiB or more (32-bit lane offsets).  LBM_EUNSUPPORTED for the
  * restrictions of sec. 3 (delta-equilibrium needs zero-centred storage; the cumulant space
  * admits no delta-equilibrium), absolute storage with the shallow-water equilibrium, D2Q9 with
  * nz != 1, the shallow-water equilibria on a 3-D stencil, Zhou's in cumulant space, Venturi's

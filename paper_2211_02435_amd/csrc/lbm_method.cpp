@@ -423,7 +423,9 @@ lbm_status validate(const lbm_params *p) {
   }
   if (!p->periodic[0] || !p->periodic[1] || !p->periodic[2])
     return fail(LBM_EUNSUPPORTED, "only periodic boundaries are implemented");
+  // cell indices in natural order (readers, force fields, diagnostics) are 32-bit
   const double ncells = double(p->nx) * double(p->ny) * double(p->nz);
+  if (ncells >= 4294967296.0) return fail(LBM_EUNSUPPORTED, "a box must have fewer than 2^32 cells");
   if (p->layout < LBM_LAYOUT_AUTO || p->layout > LBM_LAYOUT_ROWS) return fail(LBM_EINVAL, "layout out of range");
   {
     uint64_t ps, zs, ys, elems;

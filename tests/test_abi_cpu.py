@@ -82,6 +82,9 @@ def test_valid_parameter_sets():
     (dict(stencil="D3Q27", space="central", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D2Q9", space="cumulant", equilibrium="swe", gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(dims=(65536, 4096, 2), storage="f32", layout="rows"), lbm.LBM_EUNSUPPORTED),
+    # 2^32 cells of D3Q19 in F16 with AA: 163 GB, small z-planes, but 32-bit cell indices
+    (dict(stencil="D3Q19", space="raw", dims=(2048, 2048, 1024), storage="f16", streaming="aa",
+          omegas=O.regularized_rates("D3Q19", 1.2)), lbm.LBM_EUNSUPPORTED),
     (dict(layout="diagonal"), None),
     (dict(space="srt", omegas=np.r_[np.zeros(4), np.full(22, 1.2), [1.3]]), lbm.LBM_EINVAL),
     (dict(stencil="D2Q9", space="srt", omegas=np.r_[np.zeros(3), np.full(6, 1.2)], equilibrium="swe",
