@@ -297,6 +297,44 @@ def test_batch_matches_single_boxes_and_oracle():
             off += single.size
 
 
+def test_batch_launch_shapes_and_autotune_leave_results_unchanged():
+    """Every tile size, tile order and LDS reserve of the ensemble sweep gives bit-identical
+    populations; the autotuner leaves the state and the step counter alone and picks one of
+    the candidates; out-of-range shapes are rejected."""
+    dims = [(20, 12, 9), (16, 16, 16), (9, 7, 5)]
+    om = [_rates("D3Q27", "reg"), O.regularized_rates("D3Q27", 1.3), _rates("D3Q27", "gen", seed=4)]
+    rhos, us = [], []
+    for k, (nx, ny, nz) in enumerate(dims):
+        r, u = W.random_near_equilibrium_fields((nz, ny, nx), seed=20 + k, drho=5e-3, umax=0.04)
+        rhos.append(r.ravel())
+        us.append(u.ravel())  # box by box, each (3, nz, ny, nx)
+    rho = np.concatenate(rhos)
+    u = np.concatenate(us)
+    ref = None
+    for threads, swz, lds in ((256, 1, 0), (128, 0, 0), (512, 1, 32768), (64, 1, 16384)):
+        bat = lbm.Batch("D3Q27", "central", dims, om, storage="f32")
+        bat.lbm_batch_set_launch(threads, swz, lds)
+        assert bat.lbm_batch_get_launch() == (threads, swz, lds)
+        bat.lbm_batch_init_equilibrium(rho, u)
+        bat.lbm_batch_step(3)
+        got = bat.lbm_batch_get_populations()
+        if ref is None:
+            ref = got
+        np.testing.assert_array_equal(got, ref)
+    bat = lbm.Batch("D3Q27", "central", dims, om, storage="f32")
+    bat.lbm_batch_init_equilibrium(rho, u)
+    bat.lbm_batch_step(1)
+    before = bat.lbm_batch_get_populations()
+    threads, swz, lds = bat.lbm_batch_autotune()
+    assert threads in (128, 256, 512) and swz in (0, 1) and lds in (0, 16384, 24576, 32768, 40960)
+    np.testing.assert_array_equal(bat.lbm_batch_get_populations(), before)
+    bat.lbm_batch_step(2)
+    np.testing.assert_array_equal(bat.lbm_batch_get_populations(), ref)
+    for bad in ((96, 1, 0), (1024, 1, 0), (256, 1, -1), (256, 1, 70000)):
+        with pytest.raises(lbm.LbmError):
+            bat.lbm_batch_set_launch(*bad)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
@@ -399,3 +437,28 @@ def test_absolute_storage_fp64_matches_oracle(space, streaming):
     err = np.abs(lat.lbm_get_populations() - O.step(m, df0, 5)).max()
     print("absolute storage %s %s: max|d df| = %.3e" % (space, streaming, err))
     assert err <= 1e-13
+
+
+def test_tgv128_fp32_and_fp64_against_the_oracle_reference():
+    """The 128^3 copy of the D3Q27 cumulant Taylor-Green workload (u0 = 0.05, the 512^3 rates),
+    200 steps, against the FP64 oracle's velocity and density at 4096 sampled cells
+    (tests/golden/tgv128_cumulant_oracle.npz, written by make_tgv128_reference.py from the
+    oracle alone): FP32 relative L2 velocity error <= 1e-5, FP64 <= 1e-10."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "tgv128_cumulant_oracle.npz"))
+    n, steps, u0 = int(ref["n"]), int(ref["steps"]), float(ref["u0"])
+    om = O.regularized_rates("D3Q27", W.re_to_omega(u0, 512, 1600.0))
+    rho, u = W.tgv3d_fields(n, u0=u0)
+    zz, yy, xx = np.meshgrid(ref["z"], ref["y"], ref["x"], indexing="ij")
+    for storage, bar in (("f32", 1e-5), ("f64", 1e-10)):
+        lat = _lattice("D3Q27", "cumulant", om, (n, n, n), storage=storage)
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_step(steps)
+        rg, ug = lat.lbm_macroscopic()
+        lat.close()
+        us = ug[:, zz, yy, xx]
+        rel = np.linalg.norm(us - ref["u"]) / np.linalg.norm(ref["u"])
+        drho = np.abs(rg[zz, yy, xx] - ref["rho"]).max()
+        print("TGV 128^3 x %d %s: relative L2 velocity error %.3e, max |d rho| %.3e" % (steps, storage, rel, drho))
+        assert rel <= bar
+        assert drho <= (1e-6 if storage == "f32" else 1e-12)
