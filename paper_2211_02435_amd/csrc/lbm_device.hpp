@@ -268,8 +268,11 @@ struct Relax {
   T b5[3][3];
   T b6;
   // cross-order blocks (orthogonal raw bases), applied to the pre-relaxation deviations by
-  // the CROSS kernels: orders 2 -> 4, 3 -> 5, 2 -> 6 and 4 -> 6
+  // the CROSS kernels: orders 1 -> 3, 2 -> 4, 1 -> 5, 3 -> 5, 2 -> 6 and 4 -> 6 (order 1 is
+  // nonzero only with a body force)
+  T c31[7][3];
   T c42[6][6];
+  T c51[3][3];
   T c53[3][7];
   T c62[6];
   T c64[6];
@@ -585,12 +588,20 @@ LBM_HD void he_source(T *src, const T *fe, const T *u, const T *F, T rinv) {
 
 enum ForceModel { FORCE_GUO = 0, FORCE_HE = 1 };
 
-// Cross-order part of the relaxation for a basis whose polynomials mix orders (weighted-
-// orthogonal): x holds c42 v2, c53 v3 and c62 v2 + c64 v4 at the order-4, -5 and -6 entries,
-// from the pre-relaxation deviations v (other entries untouched).
-template <int S, class T>
+// Cross-order part of the relaxation for a basis whose polynomials mix orders (the orthogonal
+// bases): x holds c31 v1 at the order-3 entries, c42 v2 at order 4, c53 v3 + c51 v1 at order 5
+// and c62 v2 + c64 v4 at order 6, from the pre-relaxation deviations v (other entries
+// untouched).  v1 is -F/2 with a body force, else zero.
+template <int S, class T, bool FORCE>
 LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
+  constexpr int e1[3] = {1, 3, 9};  // x, y, z
   if constexpr (Lat<S>::D == 3) {
+    sfor<7>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      T acc = T(0);
+      if constexpr (FORCE) sfor<3>([&](auto K) { acc += R.c31[j][K] * v[e1[K]]; });
+      x[o3_3d(j)] = acc;
+    });
     sfor<6>([&](auto J) {
       constexpr int j = decltype(J)::value;
       T acc = T(0);
@@ -602,6 +613,7 @@ LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
         constexpr int j = decltype(J)::value;
         T acc = T(0);
         sfor<7>([&](auto K) { acc += R.c53[j][K] * v[o3_3d(K)]; });
+        if constexpr (FORCE) sfor<3>([&](auto K) { acc += R.c51[j][K] * v[e1[K]]; });
         x[o5_3d(j)] = acc;
       });
       T acc = T(0);
@@ -609,6 +621,10 @@ LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
       x[26] = acc;
     }
   } else {
+    sfor<2>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      x[o3_2d(j)] = FORCE ? R.c31[j][0] * v[1] + R.c31[j][1] * v[3] : T(0);
+    });
     x[8] = R.c42[0][0] * v[o2_2d(0)] + R.c42[0][1] * v[o2_2d(1)] + R.c42[0][2] * v[o2_2d(2)];
   }
 }
@@ -626,8 +642,8 @@ LBM_HD void cross_orders(T *x, const T *v, const Relax<T> &R) {
 template <int S, int SP, int EQ, bool REG, class T, bool FORCE = false, bool CROSS = false>
 LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullptr, int fmodel = FORCE_GUO) {
   static_assert(!(FORCE && REG), "the forced collision uses the general kernel");
-  static_assert(!CROSS || (SP == RAW && !REG && !FORCE && S != D3Q15),
-                "the cross-order blocks belong to the unforced general raw-moment kernel");
+  static_assert(!CROSS || (SP == RAW && !REG && S != D3Q15),
+                "the cross-order blocks belong to the general raw-moment kernel");
   constexpr int D = Lat<S>::D;
   constexpr int G = Lat<S>::G;
   constexpr int EX = 1, EY = 3, EZ = 9;
@@ -700,7 +716,17 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
       if (central) binomial<S>(fs, -u[0], -u[1], -u[2]);
       T wfs[G];
       sfor<G>([&](auto E) { wfs[E] = fs[E]; });
-      relax<S, false>(wfs, R);
+      if constexpr (CROSS) {
+        T xf[G];
+        cross_orders<S, T, true>(xf, fs, R);
+        relax<S, false>(wfs, R);
+        sfor<G>([&](auto E) {
+          constexpr int e = decltype(E)::value;
+          if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 3) wfs[e] += xf[e];
+        });
+      } else {
+        relax<S, false>(wfs, R);
+      }
       sfor<G>([&](auto E) {
         constexpr int e = decltype(E)::value;
         if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 2) vv[e] += T(0.5) * (fs[e] + wfs[e]);
@@ -712,11 +738,11 @@ LBM_HD void collide_moments(T *m, const Relax<T> &R, T grav, const T *F = nullpt
   if constexpr (SP == RAW) {
     if constexpr (CROSS) {
       T x[G];
-      cross_orders<S>(x, v, R);
+      cross_orders<S, T, FORCE>(x, v, R);
       relax<S, false>(v, R);
       sfor<G>([&](auto E) {
         constexpr int e = decltype(E)::value;
-        if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 4) v[e] += x[e];
+        if constexpr (Lat<S>::has_mono_e(e) && Lat<S>::ord(e) >= 3) v[e] += x[e];
       });
     } else {
       relax<S, REG>(v, R);

@@ -12,6 +12,7 @@ struct KTable {
   static const void *sweep_literal(int sp, int form);
   static const void *sweep_force(int sp, int pat);
   static const void *sweep_cross(int pat);
+  static const void *sweep_force_cross(int pat);
   static const void *init(int sp, int eq, int gm);
   static const void *exporter(int gm);
   static const void *importer(int gm);
@@ -25,6 +26,7 @@ const void *sweep_mfma_fn(int s, int store, int sp, int reg);
 const void *sweep_literal_fn(int s, int store, int sp, int form);
 const void *sweep_force_fn(int s, int store, int sp, int pat);
 const void *sweep_cross_fn(int s, int store, int pat);
+const void *sweep_force_cross_fn(int s, int store, int pat);
 const void *init_fn(int s, int store, int sp, int eq, int gm);
 const void *export_fn(int s, int store, int gm);
 const void *import_fn(int s, int store, int gm);

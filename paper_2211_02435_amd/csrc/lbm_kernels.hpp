@@ -249,7 +249,7 @@ __global__ void __launch_bounds__(512) sweep_kernel(SweepArgs<ST, CT> a) {
       F[2] += a.ffield[2 * nc + cell];
     }
     if constexpr (L::D == 2) F[2] = CT(0);
-    collide<S, SP, EQ, REG, CT, true>(g, a.R, a.grav, F, a.force_model);
+    collide<S, SP, EQ, REG, CT, true, CROSS>(g, a.R, a.grav, F, a.force_model);
   } else {
     collide<S, SP, EQ, REG, CT, false, CROSS>(g, a.R, a.grav);
   }

@@ -273,10 +273,12 @@ lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *
       A[size_t(i) * q + k] = acc;
     }
   auto ord = [&](int e) { return e % 3 + (e / 3) % 3 + e / 9; };
-  // order couplings the kernels apply: within an order, and (weighted-orthogonal basis) from
-  // orders 2 -> 4, 2 -> 6, 4 -> 6, 3 -> 5; columns of the conserved orders meet zero deviations
+  // order couplings the kernels apply: within an order, and (orthogonal bases) from orders
+  // 1 -> 3, 1 -> 5, 2 -> 4, 2 -> 6, 4 -> 6, 3 -> 5; order 0 meets zero deviations, and order 1
+  // nonzero ones only with a body force
   auto coupled = [](int oi, int ok) {
-    return oi == ok || ok <= 1 || (oi == 4 && ok == 2) || (oi == 6 && (ok == 2 || ok == 4)) || (oi == 5 && ok == 3);
+    return oi == ok || ok == 0 || oi <= 1 || (oi == 3 && ok == 1) || (oi == 5 && (ok == 1 || ok == 3)) ||
+           (oi == 4 && ok == 2) || (oi == 6 && (ok == 2 || ok == 4));
   };
   for (int i = 0; i < q; ++i)
     for (int k = 0; k < q; ++k)
@@ -301,6 +303,11 @@ lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *
     for (int j = 0; j < 3; ++j)
       for (int k = 0; k < 3; ++k) out->b5[j][k] = bval(kO5_3[j], kO5_3[k]);
     out->b6 = bval(26, 26);
+    const int o1[3] = {1, 3, 9};
+    for (int j = 0; j < 7; ++j)
+      for (int k = 0; k < 3; ++k) out->c31[j][k] = bval(kO3_3[j], o1[k]);
+    for (int j = 0; j < 3; ++j)
+      for (int k = 0; k < 3; ++k) out->c51[j][k] = bval(kO5_3[j], o1[k]);
     for (int j = 0; j < 6; ++j)
       for (int k = 0; k < 6; ++k) out->c42[j][k] = bval(kO4_3[j], kO2_3[k]);
     for (int j = 0; j < 3; ++j)
@@ -316,6 +323,8 @@ lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *
       for (int k = 0; k < 2; ++k) out->b3[j][k] = bval(kO3_2[j], kO3_2[k]);
     out->b4[0][0] = bval(8, 8);
     for (int k = 0; k < 3; ++k) out->c42[0][k] = bval(8, kO2_2[k]);
+    for (int j = 0; j < 2; ++j)
+      for (int k = 0; k < 2; ++k) out->c31[j][k] = bval(kO3_2[j], k == 0 ? 1 : 3);
   }
   double cmax = 0.0;
   for (int j = 0; j < 6; ++j)
@@ -324,6 +333,12 @@ lbm_status relaxation_blocks(int s, int basis, const double *omegas, RelaxHost *
     for (int k = 0; k < 7; ++k) cmax = std::fmax(cmax, std::fabs(out->c53[j][k]));
   for (int k = 0; k < 6; ++k) cmax = std::fmax(cmax, std::fmax(std::fabs(out->c62[k]), std::fabs(out->c64[k])));
   out->cross = cmax > 1e-14;
+  double c1 = 0.0;
+  for (int j = 0; j < 7; ++j)
+    for (int k = 0; k < 3; ++k) c1 = std::fmax(c1, std::fabs(out->c31[j][k]));
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) c1 = std::fmax(c1, std::fabs(out->c51[j][k]));
+  out->cross1 = c1 > 1e-14;
   // regularized: every block into an order >= 3 (from the orders >= 2 the kernels use) is zero
   double hi = 0.0;
   for (int i = 0; i < q; ++i)
@@ -375,8 +390,6 @@ lbm_status validate(const lbm_params *p) {
     if (p->arithmetic != LBM_ARITH_DEVIATION)
       return fail(LBM_EUNSUPPORTED, "the orthogonal bases run with the deviation arithmetic");
     if (p->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "no orthogonal basis for D3Q15");
-    if (p->force[0] != 0.0 || p->force[1] != 0.0 || p->force[2] != 0.0)
-      return fail(LBM_EUNSUPPORTED, "no body force with the orthogonal bases");
   }
   if (p->stencil == LBM_D3Q15) {
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)

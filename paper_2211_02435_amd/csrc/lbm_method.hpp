@@ -16,14 +16,18 @@ struct RelaxHost {
   double b4[6][6];
   double b5[3][3];
   double b6;
-  // cross-order blocks of a basis whose polynomials mix orders (weighted-orthogonal):
-  // dm*_4 += c42 dm_2, dm*_5 += c53 dm_3, dm*_6 += c62 . dm_2 + c64 . dm_4 (pre-relaxation
-  // deviations; the conserved orders carry none without a force)
+  // cross-order blocks of a basis whose polynomials mix orders (the orthogonal bases):
+  // dm*_3 += c31 dm_1, dm*_4 += c42 dm_2, dm*_5 += c53 dm_3 + c51 dm_1,
+  // dm*_6 += c62 . dm_2 + c64 . dm_4 (pre-relaxation deviations; the first-order deviations
+  // are nonzero only with a body force, the zeroth-order ones never)
+  double c31[7][3];
   double c42[6][6];
+  double c51[3][3];
   double c53[3][7];
   double c62[6];
   double c64[6];
-  bool cross;        // some cross-order block is nonzero
+  bool cross;        // some cross-order block between orders >= 2 is nonzero
+  bool cross1;       // some block from order 1 (c31, c51) is nonzero: acts only with a force
   bool regularized;  // every block of order >= 3 vanishes (all those rates equal 1)
 };
 

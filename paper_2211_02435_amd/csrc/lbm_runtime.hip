@@ -51,6 +51,7 @@ const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sw
 const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
 const void *sweep_force_fn(int s, int store, int sp, int pat) { LBM_TABLE_CALL(sweep_force, sp, pat) }
 const void *sweep_cross_fn(int s, int store, int pat) { LBM_TABLE_CALL(sweep_cross, pat) }
+const void *sweep_force_cross_fn(int s, int store, int pat) { LBM_TABLE_CALL(sweep_force_cross, pat) }
 const void *init_fn(int s, int store, int sp, int eq, int gm) { LBM_TABLE_CALL(init, sp, eq, gm) }
 const void *export_fn(int s, int store, int gm) { LBM_TABLE_CALL(exporter, gm) }
 const void *import_fn(int s, int store, int gm) { LBM_TABLE_CALL(importer, gm) }
@@ -239,6 +240,10 @@ static SweepArgs<ST, CT> make_sweep_args(const lbm_ctx *c, const void *src, void
   for (int j = 0; j < 3; ++j)
     for (int k = 0; k < 3; ++k) a.R.b5[j][k] = CT(c->R.b5[j][k]);
   a.R.b6 = CT(c->R.b6);
+  for (int j = 0; j < 7; ++j)
+    for (int k = 0; k < 3; ++k) a.R.c31[j][k] = CT(c->R.c31[j][k]);
+  for (int j = 0; j < 3; ++j)
+    for (int k = 0; k < 3; ++k) a.R.c51[j][k] = CT(c->R.c51[j][k]);
   for (int j = 0; j < 6; ++j)
     for (int k = 0; k < 6; ++k) a.R.c42[j][k] = CT(c->R.c42[j][k]);
   for (int j = 0; j < 3; ++j)
@@ -331,7 +336,9 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     dst = c->buf[0];
   }
   if (forced(c) && sp_override < 0) {
-    const void *fn = sweep_force_fn(c->s, c->store, sp, pat);
+    // with a force the first-order deviations are -F/2, so the blocks from order 1 act too
+    const bool cross = c->R.cross || c->R.cross1;
+    const void *fn = cross ? sweep_force_cross_fn(c->s, c->store, pat) : sweep_force_fn(c->s, c->store, sp, pat);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no forced kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
   } else if (c->literal && sp_override < 0) {
@@ -637,8 +644,6 @@ extern "C" lbm_status lbm_set_force_field(lbm_ctx *c, const double *F) {
   if (c->eq != MAXWELL) return fail(LBM_EUNSUPPORTED, "the body force is implemented with the Maxwellian equilibrium");
   if (c->literal) return fail(LBM_EUNSUPPORTED, "the body force runs with the deviation arithmetic");
   if (c->transform == LBM_TRANSFORM_DENSE_MFMA) return fail(LBM_EUNSUPPORTED, "no body force in the MFMA ablation");
-  if (c->R.cross || c->p.basis != LBM_BASIS_GRADED)
-    return fail(LBM_EUNSUPPORTED, "no body force with the orthogonal bases");
   const size_t n = 3 * size_t(c->ncells);
   std::vector<double> h(n);
   if (is_device_ptr(F)) HIPCHECK(hipMemcpy(h.data(), F, n * sizeof(double), hipMemcpyDeviceToHost), "force copy");
