@@ -199,7 +199,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (a box would shard "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a box would shard "
               "as z-slabs with one halo exchange per step; not built).", file=sys.stderr)
         sys.exit(2)
 

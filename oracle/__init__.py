@@ -1,8 +1,8 @@
 """Plain FP64 CPU oracle for the zero-centred MRT lattice Boltzmann sweep.
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
-execute anything in this package: it exists so that tests/, the smoke check of
-the graft entry point and the cpu_baseline leg of bench.py can compare the HIP
+execute anything in this package: it exists so that tests/, the smoke check in
+__graft_entry__.smoke() and the cpu_baseline leg of bench.py can compare the HIP
 kernels against the definitions of Hennig, Holzer and Ruede, "Advanced
 Automatic Code Generation for Multiple Relaxation-Time Lattice Boltzmann
 Methods" (arXiv 2211.02435).
