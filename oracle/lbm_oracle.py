@@ -11,6 +11,9 @@ tests/test_oracle_*.py check it against something other than itself):
 
   Stencil / weights          sec. 2.1 (D2Q9/D3Q15/D3Q19/D3Q27, xi_0 = 0)
         pin: w == M^-1 m0 (sec. 2.4, background equals the weights), isotropy sums
+  D3Q15 moment set           one monomial per exponent-parity class of the mixed monomials
+        pin: the classes by brute force over the velocities; the raw (polynomial) and
+             central (Maxwellian) equilibria's fourth moments worked out by hand
   weighted_orthogonal_matrix WO-MRT / O-MRT bases (sec. 2.3.1): Gram-Schmidt under the weights
         or the plain sum
         pin: orthogonality by brute force, D2Q9 / D3Q27 Hermite product forms (WO), the
