@@ -203,7 +203,7 @@ lbm_status lbm_params_default(lbm_params *p);
  * nz != 1, the shallow-water equilibria on a 3-D stencil, Zhou's in cumulant space, Venturi's
  * outside central and cumulant space, non-periodic
  * axes, SRT with unequal rates (EINVAL) or the shallow-water equilibrium, LITERAL arithmetic
- * outside D2Q9/D3Q27, F64/F32, pull, Maxwellian, a body force with LITERAL arithmetic or a
+ * outside D2Q9/D3Q27, pull, Maxwellian, a body force with LITERAL arithmetic or a
  * shallow-water equilibrium, D3Q15 with another equilibrium or LITERAL arithmetic, and the
  * orthogonal bases outside their domain (lbm_basis).
  * Absolute storage keeps f = df + w in the buffers (the "absolute" storage format of the

@@ -415,7 +415,6 @@ lbm_status validate(const lbm_params *p) {
   if (p->arithmetic == LBM_ARITH_LITERAL) {
     if (p->stencil != LBM_D2Q9 && p->stencil != LBM_D3Q27)
       return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for D2Q9 and D3Q27");
-    if (p->storage == LBM_STORE_F16) return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic needs F64 or F32 storage");
     if (p->streaming != LBM_STREAM_PULL) return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic runs with pull streaming");
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
       return fail(LBM_EUNSUPPORTED, "LITERAL arithmetic is implemented for the Maxwellian equilibrium");

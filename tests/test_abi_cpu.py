@@ -90,7 +90,6 @@ def test_valid_parameter_sets():
     (dict(stencil="D2Q9", space="srt", omegas=np.r_[np.zeros(3), np.full(6, 1.2)], equilibrium="swe",
           gravity=0.1), lbm.LBM_EUNSUPPORTED),
     (dict(stencil="D3Q19", space="raw", arithmetic="literal"), lbm.LBM_EUNSUPPORTED),
-    (dict(space="raw", arithmetic="literal", storage="f16"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="aa"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="esoteric"), lbm.LBM_EUNSUPPORTED),
     (dict(space="raw", arithmetic="literal", streaming="twist"), lbm.LBM_EUNSUPPORTED),
@@ -131,7 +130,7 @@ def test_srt_and_literal_parameter_sets():
             for zc, form in ((0, "default"), (1, "absolute"), (1, "delta"), (1, "default")):
                 if sp == "cumulant" and form == "delta":
                     continue
-                for store in ("f64", "f32"):
+                for store in ("f64", "f32", "f16"):
                     p = _p(stencil=st, space=sp, omegas=om, zero_centered=zc, eq_form=form, storage=store,
                            arithmetic="literal")
                     assert lbm.lbm_validate(p) == 0, (st, sp, zc, form, store, lbm.last_error())

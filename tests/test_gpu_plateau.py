@@ -93,9 +93,9 @@ def test_fp16_storage_plateau(space):
     under half an ulp every population rounds back to w_i and the vortex is erased (E = 0).
     Zero-centred populations keep FP16's relative resolution: the decay follows the analytic
     curve at 20 000 steps and stalls only at E/E0 ~ 1e-6."""
-    cols = dict(PL.COLUMNS_F16)
-    a = PL.run(space, cols["absolute storage"], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
-    z = PL.run(space, cols["zero-centred, delta f_eq"], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
+    cols = dict(PL.columns("f16"))
+    a = PL.run(space, cols[PL.ABS_DEVIATION[0]], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
+    z = PL.run(space, cols[ZC_DEV], n=N, nz=1, steps=STEPS, storage="f16", every=20000)
     analytic20 = math.exp(-4.0 / 6.0 * (2.0 * math.pi / N) ** 2 * 20000)
     a20, z20 = dict(a["trace"])[20000], dict(z["trace"])[20000]
     print("F16 %-9s at 20000: analytic %.2e absolute %.2e zero-centred %.2e; final absolute %.2e "
