@@ -151,8 +151,7 @@ typedef enum { LBM_FORCE_GUO = 0, LBM_FORCE_HE = 1 } lbm_force_model;
  * polynomial.  Its polynomials mix orders, so the relaxation couples a moment to lower orders
  * of the same parity.  ORTHOGONAL (O-MRT): the same with the plain sum over the velocities
  * (on D2Q9 the polynomials of Lallemand and Luo).  The orthogonal bases need the raw-moment
- * space, the Maxwellian equilibrium, DEVIATION arithmetic and D2Q9, D3Q19 or D3Q27
- * (LBM_EUNSUPPORTED otherwise); with every rate equal to 1 they equal GRADED.  With a body
+ * space, the Maxwellian equilibrium and D2Q9, D3Q19 or D3Q27 (LBM_EUNSUPPORTED otherwise); with every rate equal to 1 they equal GRADED.  With a body
  * force the first-order deviations (-F/2) also reach orders 3 and 5. */
 typedef enum { LBM_BASIS_GRADED = 0, LBM_BASIS_WEIGHTED_ORTHOGONAL = 1, LBM_BASIS_ORTHOGONAL = 2 } lbm_basis;
 

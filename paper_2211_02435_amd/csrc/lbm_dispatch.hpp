@@ -10,6 +10,7 @@ struct KTable {
   static const void *sweepv(int sp, int eq, int reg, int pat);
   static const void *sweep_mfma(int sp, int reg);
   static const void *sweep_literal(int sp, int form);
+  static const void *sweep_literal_cross(int form);
   static const void *sweep_force(int sp, int pat);
   static const void *sweep_cross(int pat);
   static const void *sweep_force_cross(int pat);
@@ -24,6 +25,7 @@ const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat);
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat);
 const void *sweep_mfma_fn(int s, int store, int sp, int reg);
 const void *sweep_literal_fn(int s, int store, int sp, int form);
+const void *sweep_literal_cross_fn(int s, int store, int form);
 const void *sweep_force_fn(int s, int store, int sp, int pat);
 const void *sweep_cross_fn(int s, int store, int pat);
 const void *sweep_force_cross_fn(int s, int store, int pat);

@@ -138,9 +138,10 @@ LBM_HD void lit_srt(T *g, const Relax<T> &R) {
 }
 
 // the literal collision; g holds f (LIT_A) or df (LIT_B, LIT_C) in grid order
-template <int S, int SP, int FORM, class T>
+template <int S, int SP, int FORM, class T, bool CROSS = false>
 LBM_HD void collide_literal(T *g, const Relax<T> &R) {
   static_assert(!(SP == CUMULANT && FORM == LIT_B), "no delta-equilibrium for the nonlinear cumulant transform");
+  static_assert(!CROSS || SP == RAW, "the cross-order blocks belong to the orthogonal raw-moment bases");
   if constexpr (SP == SRT) {
     lit_srt<S, FORM>(g, R);
     return;
@@ -197,7 +198,18 @@ LBM_HD void collide_literal(T *g, const Relax<T> &R) {
       constexpr int e = decltype(E)::value;
       v[e] = L::ord(e) < 2 ? T(0) : g[e] - qeq[e];
     });
-    relax<S, false>(v, R);
+    if constexpr (CROSS) {
+      // orthogonal raw basis: the blocks between orders (orders 0 and 1 carry no deviation)
+      T x[G];
+      cross_orders<S, T, false>(x, v, R);
+      relax<S, false>(v, R);
+      sfor<G>([&](auto E) {
+        constexpr int e = decltype(E)::value;
+        if constexpr (L::has_mono_e(e) && L::ord(e) >= 3) v[e] += x[e];
+      });
+    } else {
+      relax<S, false>(v, R);
+    }
     sfor<G>([&](auto E) {
       constexpr int e = decltype(E)::value;
       if constexpr (!L::has_mono_e(e)) g[e] = T(0);
@@ -217,7 +229,7 @@ LBM_HD void collide_literal(T *g, const Relax<T> &R) {
 }
 
 // the literal sweep: pull streaming, one cell per thread, the buffers hold f (LIT_A) or df
-template <int S, int SP, int FORM, class ST, class CT>
+template <int S, int SP, int FORM, class ST, class CT, bool CROSS = false>
 __global__ void __launch_bounds__(512) sweep_literal_kernel(SweepArgs<ST, CT> a) {
   using L = Lat<S>;
   const CellPos p = tile_cell_args(a, 1);
@@ -230,7 +242,7 @@ __global__ void __launch_bounds__(512) sweep_literal_kernel(SweepArgs<ST, CT> a)
     constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
     g[L::gidx(i)] = CT(ldp(a.src, uint64_t(i) * a.L.ps + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
   });
-  collide_literal<S, SP, FORM, CT>(g, a.R);
+  collide_literal<S, SP, FORM, CT, CROSS>(g, a.R);
   sfor<L::Q>([&](auto I) {
     constexpr int i = decltype(I)::value;
     stp(a.dst, uint64_t(i) * a.L.ps + nb.zpart(0, 1), nb.lane(0, 0, 1), ST(g[L::gidx(i)]));

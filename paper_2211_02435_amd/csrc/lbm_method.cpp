@@ -387,8 +387,6 @@ lbm_status validate(const lbm_params *p) {
     if (p->space != LBM_SPACE_RAW) return fail(LBM_EUNSUPPORTED, "the orthogonal bases are raw-moment bases");
     if (p->equilibrium != LBM_EQ_MAXWELLIAN)
       return fail(LBM_EUNSUPPORTED, "the orthogonal bases run with the Maxwellian equilibrium");
-    if (p->arithmetic != LBM_ARITH_DEVIATION)
-      return fail(LBM_EUNSUPPORTED, "the orthogonal bases run with the deviation arithmetic");
     if (p->stencil == LBM_D3Q15) return fail(LBM_EUNSUPPORTED, "no orthogonal basis for D3Q15");
   }
   if (p->stencil == LBM_D3Q15) {

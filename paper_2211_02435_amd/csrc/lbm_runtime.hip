@@ -49,6 +49,7 @@ const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_T
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
 const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
 const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
+const void *sweep_literal_cross_fn(int s, int store, int form) { LBM_TABLE_CALL(sweep_literal_cross, form) }
 const void *sweep_force_fn(int s, int store, int sp, int pat) { LBM_TABLE_CALL(sweep_force, sp, pat) }
 const void *sweep_cross_fn(int s, int store, int pat) { LBM_TABLE_CALL(sweep_cross, pat) }
 const void *sweep_force_cross_fn(int s, int store, int pat) { LBM_TABLE_CALL(sweep_force_cross, pat) }
@@ -342,7 +343,7 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     if (!fn) return fail(LBM_EUNSUPPORTED, "no forced kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
   } else if (c->literal && sp_override < 0) {
-    const void *fn = sweep_literal_fn(c->s, c->store, sp, c->form);
+    const void *fn = c->R.cross ? sweep_literal_cross_fn(c->s, c->store, c->form) : sweep_literal_fn(c->s, c->store, sp, c->form);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no literal-arithmetic kernel for this method");
     HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
   } else if (c->transform == LBM_TRANSFORM_DENSE_MFMA && sp_override < 0) {

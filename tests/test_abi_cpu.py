@@ -177,7 +177,6 @@ def test_weighted_orthogonal_basis_parameter_sets():
                     assert lbm.lbm_validate(p) == 0, (st, store, stream, basis, lbm.last_error())
     om = O.regularized_rates("D3Q27", 1.6)
     for kw in (dict(space="central"), dict(space="cumulant"), dict(space="srt", omegas=np.r_[np.zeros(4), np.full(23, 1.6)]),
-               dict(space="raw", arithmetic="literal"),
                dict(stencil="D3Q15", space="raw", omegas=O.regularized_rates("D3Q15", 1.6)),
                dict(stencil="D2Q9", space="raw", omegas=O.regularized_rates("D2Q9", 1.6), equilibrium="swe",
                     gravity=0.1)):
@@ -187,6 +186,7 @@ def test_weighted_orthogonal_basis_parameter_sets():
         assert lbm.lbm_validate(_p(basis="orthogonal", **kw)) == lbm.LBM_EUNSUPPORTED, kw
     for basis in ("weighted_orthogonal", "orthogonal"):
         assert lbm.lbm_validate(_p(space="raw", omegas=om, basis=basis, force=(1e-5, 0, 0), force_model="he")) == 0
+        assert lbm.lbm_validate(_p(space="raw", omegas=om, basis=basis, arithmetic="literal", zero_centered=0)) == 0
     p = _p(space="raw", omegas=om)
     p.basis = 3
     assert lbm.lbm_validate(p) == lbm.LBM_EINVAL

@@ -133,3 +133,27 @@ def test_literal_and_deviation_agree_in_fp64():
         lat.lbm_step(4)
         outs.append(lat.lbm_get_populations())
     assert np.abs(outs[0] - outs[1]).max() <= 1e-14
+
+
+@pytest.mark.parametrize("stencil", ["D2Q9", "D3Q27"])
+@pytest.mark.parametrize("basis", ["weighted_orthogonal", "orthogonal"])
+@pytest.mark.parametrize("zc,eq_form,oracle_form", FORMS)
+def test_literal_forms_in_the_orthogonal_bases_match_oracle(stencil, basis, zc, eq_form, oracle_form):
+    """The literal raw-moment forms with a weighted-orthogonal or orthogonal basis (cross-order
+    relaxation blocks), general rates, FP64, against the oracle's forms."""
+    dims = RAGGED2 if stencil == "D2Q9" else RAGGED3
+    om = _rates(stencil, "raw", "gen")
+    m = O.Method(stencil, "raw", om, basis=basis)
+    df0 = _noisy_state(m, dims)
+    lat = lbm.Lattice(stencil, "raw", om, dims, storage="f64", zero_centered=bool(zc), eq_form=eq_form,
+                      arithmetic="literal", basis=basis)
+    lat.lbm_set_populations(df0)
+    lat.lbm_step(4)
+    got = lat.lbm_get_populations()
+    if oracle_form == "absolute":
+        want = O.step(m, df0 + m.f0[:, None, None, None], 4, form="absolute") - m.f0[:, None, None, None]
+    else:
+        want = O.step(m, df0, 4, form=oracle_form)
+    err = np.abs(got - want).max()
+    print("literal %s %s %s max|d df| = %.3e" % (basis, stencil, oracle_form, err))
+    assert err <= 1e-13
