@@ -35,16 +35,20 @@ def kernel_rows(db):
     return rows
 
 
-def stats(db, match=None):
-    agg = {}
+def stats(db, match=None, last=None):
+    """Per-kernel call count and total / average / min / max duration; with `last`, only the
+    last `last` dispatches of every kernel (the timed region of a bench run that autotuned
+    or warmed up first)."""
+    per = {}
     for name, dur, _ in kernel_rows(db):
         if match and match not in name:
             continue
-        a = agg.setdefault(name, [0, 0.0, float("inf"), 0.0])
-        a[0] += 1
-        a[1] += dur
-        a[2] = min(a[2], dur)
-        a[3] = max(a[3], dur)
+        per.setdefault(name, []).append(dur)
+    agg = {}
+    for name, durs in per.items():
+        if last:
+            durs = durs[-last:]
+        agg[name] = [len(durs), float(sum(durs)), float(min(durs)), float(max(durs))]
     out = []
     for name, (n, tot, mn, mx) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
         out.append({"kernel": name, "calls": n, "total_us": tot / 1e3, "avg_us": tot / n / 1e3,
@@ -103,6 +107,7 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("db")
     s.add_argument("--match", default=None)
+    s.add_argument("--last", type=int, default=None, help="only the last N dispatches of every kernel")
     t = sub.add_parser("traffic")
     t.add_argument("--fetch", required=True)
     t.add_argument("--write", required=True)
@@ -113,7 +118,7 @@ def main(argv=None):
     t.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
-        rows = stats(a.db, a.match)
+        rows = stats(a.db, a.match, a.last)
         print("%-110s %6s %12s %10s %10s %10s" % ("kernel", "calls", "total_us", "avg_us", "min_us", "max_us"))
         for r in rows:
             print("%-110s %6d %12.1f %10.1f %10.1f %10.1f" % (r["kernel"][:110], r["calls"], r["total_us"],
