@@ -13,21 +13,10 @@ import pytest
 
 import lbm_workloads as W
 import oracle as O
+import sampled_oracle as SO
 from paper_2211_02435_amd import lbm
 
 pytestmark = pytest.mark.gpu
-
-
-def _oracle_one_step_samples(m, pts, dims, fields_at):
-    """Expected df_i(x, 1) at the sample cells: collide the neighbours x - xi_i at t = 0."""
-    st = m.st
-    nx, ny, nz = dims
-    src = (pts[:, None, :] - st.xi[None, :, :]) % np.array([nx, ny, nz])[None, None, :]
-    flat = src.reshape(-1, 3)
-    rho, u = fields_at(flat[:, 0], flat[:, 1], flat[:, 2])
-    df0 = O.equilibrium_populations(m, rho, u) - m.f0
-    out = O.collide_cells(m, df0, O.default_form(m)).reshape(len(pts), st.q, st.q)
-    return out[:, np.arange(st.q), np.arange(st.q)]  # component i of neighbour i
 
 
 def _gpu_samples(lat, pts):
@@ -60,9 +49,39 @@ def test_d3q27_cumulant_512_one_step_sampled(storage, tol):
     pts = W.sample_cells((n, n, n), 48, seed=1)
     got = _gpu_samples(lat, pts)
     m = O.Method("D3Q27", "cumulant", om)
-    want = _oracle_one_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]))
+    want = SO.one_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]))
     err = np.abs(got - want).max()
     print("D3Q27 cumulant 512^3 %s one step, %d sampled cells: max|d df| = %.3e" % (storage, len(pts), err))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("storage,streaming,tol", [("f32", "pull", 6e-8), ("f64", "pull", 3e-15),
+                                                    ("f32", "aa", 6e-8), ("f32", "esoteric", 6e-8),
+                                                    ("f32", "twist", 6e-8), ("f32", "push", 6e-8)])
+def test_d3q27_cumulant_512_three_steps_sampled(storage, streaming, tol):
+    """The timed sequence at full size: one eager step, then two steps replayed from a recorded
+    graph, so that both buffers (or both phases of an in-place pattern) are written by the
+    timed launch.  Bars: three times the one-step bars."""
+    cfg = W.WORKLOADS["d3q27_cumulant_512"]
+    n = cfg["dims"][0]
+    om = O.regularized_rates("D3Q27", cfg["omega_shear"])
+    rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
+    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, n), storage=storage, streaming=streaming)
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_autotune()
+    lat.lbm_step(1)
+    lat.lbm_graph_prepare(2)
+    lat.lbm_time_steps(2)
+    assert lat.lib.lbm_time(lat.ctx) == 3
+    pts = W.sample_cells((n, n, n), 48, seed=4)
+    got = _gpu_samples(lat, pts)
+    del lat
+    m = O.Method("D3Q27", "cumulant", om)
+    want = SO.k_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]), 3)
+    err = np.abs(got - want).max()
+    print("D3Q27 cumulant 512^3 %s %s three steps, %d sampled cells: max|d df| = %.3e"
+          % (storage, streaming, len(pts), err))
     assert err <= tol
 
 
@@ -115,7 +134,7 @@ def test_d3q19_raw_256_one_step_sampled(storage, tol):
     pts = W.sample_cells((n, n, n), 48, seed=2)
     got = _gpu_samples(lat, pts)
     m = O.Method("D3Q19", "raw", om)
-    want = _oracle_one_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]))
+    want = SO.one_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]))
     err = np.abs(got - want).max()
     print("D3Q19 raw 256^3 %s one step: max|d df| = %.3e" % (storage, err))
     assert err <= tol
@@ -139,7 +158,7 @@ def test_swe_4096_one_step_sampled(storage, tol):
 
     def fields_at(x, y, z):
         return hh[y, x], np.zeros((len(x), 3))
-    want = _oracle_one_step_samples(m, pts, (n, n, 1), fields_at)
+    want = SO.one_step_samples(m, pts, (n, n, 1), fields_at)
     err = np.abs(got - want).max()
     print("SWE 4096^2 %s one step: max|d df| = %.3e" % (storage, err))
     assert err <= tol
@@ -165,7 +184,7 @@ def test_batch_256_boxes_one_step_sampled():
             pts = W.sample_cells(d, 4, seed=int(rng.integers(1 << 30)))
             got = box[:, pts[:, 2], pts[:, 1], pts[:, 0]].T
             m = O.Method("D3Q27", "central", om)
-            want = _oracle_one_step_samples(
+            want = SO.one_step_samples(
                 m, pts, d, lambda x, y, z, b=b, e=d[0]: W.tgv3d_points(x, y, z, e, b["u0"], b["phase"]))
             worst = max(worst, float(np.abs(got - want).max()))
     print("ensemble one step, 16 boxes sampled: max|d df| = %.3e" % worst)
