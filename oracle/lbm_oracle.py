@@ -1,6 +1,6 @@
 """FP64 CPU oracle: dense definitions of the zero-centred MRT-LBM collision and streaming.
 
-TEST INFRASTRUCTURE ONLY -- imported by tests/, the graft smoke check and the
+TEST INFRASTRUCTURE ONLY -- imported by tests/, __graft_entry__.smoke() and the
 cpu_baseline leg of bench.py; never by the product path.
 
 Paper: Hennig, Holzer, Ruede, "Advanced Automatic Code Generation for Multiple
