@@ -359,8 +359,8 @@ lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms);
  * values out of range. */
 lbm_status lbm_batch_set_launch(lbm_batch *b, int threads, int swizzle, int lds_bytes);
 lbm_status lbm_batch_get_launch(const lbm_batch *b, int *threads, int *swizzle, int *lds_bytes);
-/* Times one sweep for every tile size in {128, 256, 512}, both tile orders and the LDS
- * reserves {0, 16, 24, 32, 40} KiB, and keeps the fastest.  The state and the step counter
+/* Times one sweep for every tile size in {64, 128, 256, 512}, both tile orders and the LDS
+ * reserves {0, 16, 20, 26, 32, 40, 52, 64} KiB, and keeps the fastest.  The state and the step counter
  * are left unchanged (each timed sweep writes only the other buffer).  Synchronous. */
 lbm_status lbm_batch_autotune(lbm_batch *b);
 

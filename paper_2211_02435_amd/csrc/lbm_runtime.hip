@@ -986,9 +986,12 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   const bool g0 = c->graphs;
   c->graphs = false;
   const uint64_t lups = uint64_t(c->ncells);
-  const int reps = int(std::max<uint64_t>(2, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
+  const int reps = int(std::max<uint64_t>(4, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
   double best = 1e300;
   int bb[4] = {bx0, by0, swz0, vec0 ? 1 : 0};
+  // best uncapped shape per block size (64, 128, 256, 512 threads), the starting points of phase 2
+  double best_t[4] = {1e300, 1e300, 1e300, 1e300};
+  std::array<int, 4> shape_t[4] = {};
   hipEvent_t e0, e1;
   HIPCHECK(hipEventCreate(&e0), "event");
   HIPCHECK(hipEventCreate(&e1), "event");
@@ -1020,15 +1023,24 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
       bb[2] = cd[2];
       bb[3] = cd[3];
     }
+    const int ti = cd[0] * cd[1] == 64 ? 0 : cd[0] * cd[1] == 128 ? 1 : cd[0] * cd[1] == 256 ? 2 : 3;
+    if (ms < best_t[ti]) {
+      best_t[ti] = ms;
+      shape_t[ti] = cd;
+    }
   }
-  // phase 2: occupancy cap for the best shape (dynamic LDS per block)
+  // phase 2: occupancy cap (dynamic LDS per block) on the best shape of each block size.  Fewer
+  // resident waves than the registers allow can stream faster, so the cap and the block size
+  // are chosen together; the ladder holds at most 10, 8, 6, 5, 4, 3 or 2 blocks per CU (160 KiB).
   int best_lds = 0;
-  if (st == LBM_OK) {
-    c->bx = bb[0];
-    c->by = bb[1];
-    c->swz = bb[2];
-    c->vec = bb[3] != 0;
-    for (int lds : {16384, 24576, 32768, 40960, 54272}) {
+  for (int ti = 0; ti < 4 && st == LBM_OK; ++ti) {
+    if (best_t[ti] >= 1e300) continue;
+    const std::array<int, 4> &cd = shape_t[ti];
+    c->bx = cd[0];
+    c->by = cd[1];
+    c->swz = cd[2];
+    c->vec = cd[3] != 0;
+    for (int lds : {16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
       c->lds = lds;
       for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
         if (r == 1) (void)hipEventRecord(e0, c->stream);
@@ -1043,14 +1055,18 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
       if (st != LBM_OK) break;
       if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
         std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d vec %d lds %d: %.4f ms/step\n", key.c_str(),
-                     bb[0], bb[1], bb[2], bb[3], lds, ms / reps);
+                     cd[0], cd[1], cd[2], cd[3], lds, ms / reps);
       if (ms < best) {
         best = ms;
+        bb[0] = cd[0];
+        bb[1] = cd[1];
+        bb[2] = cd[2];
+        bb[3] = cd[3];
         best_lds = lds;
       }
     }
-    c->lds = lds0;
   }
+  c->lds = lds0;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   c->cur = cur0;
@@ -1569,11 +1585,11 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
   double best = 1e300;
   int bb[3] = {bt0, swz0, lds0};
   lbm_status st = LBM_OK;
-  for (int bt : {128, 256, 512}) {
+  for (int bt : {64, 128, 256, 512}) {
     st = batch_build_tiles(b, bt);
     if (st != LBM_OK) break;
     for (int swz : {0, 1}) {
-      for (int lds : {0, 16384, 24576, 32768, 40960}) {
+      for (int lds : {0, 16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
         b->swz = swz;
         b->lds = lds;
         for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {

@@ -311,7 +311,8 @@ def test_batch_launch_shapes_and_autotune_leave_results_unchanged():
     rho = np.concatenate(rhos)
     u = np.concatenate(us)
     ref = None
-    for threads, swz, lds in ((256, 1, 0), (128, 0, 0), (512, 1, 32768), (64, 1, 16384)):
+    for threads, swz, lds in ((256, 1, 0), (128, 0, 0), (512, 1, 32768), (64, 1, 16384), (128, 1, 65536),
+                              (256, 0, 53248)):
         bat = lbm.Batch("D3Q27", "central", dims, om, storage="f32")
         bat.lbm_batch_set_launch(threads, swz, lds)
         assert bat.lbm_batch_get_launch() == (threads, swz, lds)
@@ -326,13 +327,46 @@ def test_batch_launch_shapes_and_autotune_leave_results_unchanged():
     bat.lbm_batch_step(1)
     before = bat.lbm_batch_get_populations()
     threads, swz, lds = bat.lbm_batch_autotune()
-    assert threads in (128, 256, 512) and swz in (0, 1) and lds in (0, 16384, 24576, 32768, 40960)
+    assert threads in (64, 128, 256, 512) and swz in (0, 1)
+    assert lds in (0, 16384, 20480, 26624, 32768, 40960, 53248, 65536)
     np.testing.assert_array_equal(bat.lbm_batch_get_populations(), before)
     bat.lbm_batch_step(2)
     np.testing.assert_array_equal(bat.lbm_batch_get_populations(), ref)
     for bad in ((96, 1, 0), (1024, 1, 0), (256, 1, -1), (256, 1, 70000)):
         with pytest.raises(lbm.LbmError):
             bat.lbm_batch_set_launch(*bad)
+
+
+@pytest.mark.parametrize("streaming", ["pull", "aa", "twist"])
+def test_occupancy_cap_and_autotune_leave_results_unchanged(streaming):
+    """The LDS reserve only limits how many blocks share a CU: every cap gives bit-identical
+    populations, and the autotuner (which times the caps on each block size) keeps the state."""
+    dims = (70, 9, 5)
+    om = _rates("D3Q27", "reg")
+    rho, u = W.random_near_equilibrium_fields(dims[::-1], seed=8, drho=5e-3, umax=0.04)
+    ref = None
+    for bx, by, lds in ((64, 2, 0), (64, 1, 53248), (128, 1, 65536), (256, 1, 20480)):
+        lat = lbm.Lattice("D3Q27", "cumulant", om, dims, storage="f32", streaming=streaming)
+        lat.lbm_set_launch(bx, by, 1)
+        lat.lbm_set_lds_reserve(lds)
+        assert lat.lbm_get_lds_reserve() == lds
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_step(3)
+        got = lat.lbm_get_populations()
+        if ref is None:
+            ref = got
+        np.testing.assert_array_equal(got, ref)
+    lat = lbm.Lattice("D3Q27", "cumulant", om, dims, storage="f32", streaming=streaming)
+    lat.lbm_init_equilibrium(rho, u)
+    lat.lbm_step(1)
+    before = lat.lbm_get_populations()
+    lat.lbm_autotune()
+    assert lat.lbm_get_lds_reserve() in (0, 16384, 20480, 26624, 32768, 40960, 53248, 65536)
+    np.testing.assert_array_equal(lat.lbm_get_populations(), before)
+    lat.lbm_step(2)
+    np.testing.assert_array_equal(lat.lbm_get_populations(), ref)
+    with pytest.raises(lbm.LbmError):
+        lat.lbm_set_lds_reserve(65537)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
