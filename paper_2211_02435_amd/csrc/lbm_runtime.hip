@@ -967,10 +967,13 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
           if (cby > 1 && cby / 2 >= c->ny) continue;
           cand.push_back({cbx, cby, cs, cv});
         }
-  // the sweep must leave the state unchanged: pull and push write only the other buffer; the
-  // in-place patterns run on a copy of the buffer that is restored afterwards
+  // the sweep must leave the state unchanged: pull and push write only the other buffer, so
+  // every timed sweep repeats the same src -> dst step; the in-place patterns run on a copy of
+  // the buffer that is restored afterwards and time their even and odd steps alternately, as
+  // they run, over an even number of steps
+  const bool two = two_buffers(c);
   void *saved = nullptr;
-  if (!two_buffers(c)) {
+  if (!two) {
     hipError_t e = hipMalloc(&saved, c->buf_bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -986,7 +989,8 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   const bool g0 = c->graphs;
   c->graphs = false;
   const uint64_t lups = uint64_t(c->ncells);
-  const int reps = int(std::max<uint64_t>(4, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
+  int reps = int(std::max<uint64_t>(4, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
+  reps += reps & 1;
   double best = 1e300;
   int bb[4] = {bx0, by0, swz0, vec0 ? 1 : 0};
   // best uncapped shape per block size (64, 128, 256, 512 threads), the starting points of phase 2
@@ -1002,10 +1006,11 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
     c->swz = cd[2];
     c->vec = cd[3] != 0;
     // warm-up, then time reps sweeps; pull: same src -> dst every time
+    c->t = t0;
     for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
       if (r == 1) (void)hipEventRecord(e0, c->stream);
       c->cur = cur0;
-      c->t = t0;
+      if (two) c->t = t0;
       st = one_step(c);
     }
     (void)hipEventRecord(e1, c->stream);
@@ -1042,10 +1047,11 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
     c->vec = cd[3] != 0;
     for (int lds : {16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
       c->lds = lds;
+      c->t = t0;
       for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
         if (r == 1) (void)hipEventRecord(e0, c->stream);
         c->cur = cur0;
-        c->t = t0;
+        if (two) c->t = t0;
         st = one_step(c);
       }
       (void)hipEventRecord(e1, c->stream);
