@@ -85,6 +85,56 @@ def test_d3q27_cumulant_512_three_steps_sampled(storage, streaming, tol):
     assert err <= tol
 
 
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-8), ("f64", 1e-15)])
+def test_d3q27_cumulant_512_general_rates_sampled(storage, tol):
+    """The general-rate kernel at full size (every rate of order >= 3 set to 1.3, so no
+    order is pinned to its equilibrium), one step, sampled."""
+    cfg = W.WORKLOADS["d3q27_cumulant_512"]
+    n = cfg["dims"][0]
+    st = O.stencil("D3Q27")
+    om = O.regularized_rates("D3Q27", cfg["omega_shear"])
+    om[[j for j in range(st.q) if st.order(j) >= 3]] = 1.3
+    rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
+    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, n), storage=storage)
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_autotune()
+    lat.lbm_step(1)
+    pts = W.sample_cells((n, n, n), 48, seed=5)
+    got = _gpu_samples(lat, pts)
+    del lat
+    m = O.Method("D3Q27", "cumulant", om)
+    want = SO.one_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]))
+    err = np.abs(got - want).max()
+    print("D3Q27 cumulant 512^3 general rates %s one step: max|d df| = %.3e" % (storage, err))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("storage,tol", [("f32", 2e-8), ("f64", 1e-15)])
+def test_d3q15_raw_512_three_steps_sampled(storage, tol):
+    """D3Q15 raw moments at 512^3 (the stencil's bench workload): one eager step and two
+    graph-replayed steps, sampled."""
+    cfg = W.WORKLOADS["d3q15_raw_512"]
+    n = cfg["dims"][0]
+    om = O.regularized_rates("D3Q15", cfg["omega_shear"])
+    rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
+    lat = lbm.Lattice("D3Q15", "raw", om, (n, n, n), storage=storage)
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_autotune()
+    lat.lbm_step(1)
+    lat.lbm_graph_prepare(2)
+    lat.lbm_time_steps(2)
+    pts = W.sample_cells((n, n, n), 48, seed=6)
+    got = _gpu_samples(lat, pts)
+    del lat
+    m = O.Method("D3Q15", "raw", om)
+    want = SO.k_step_samples(m, pts, (n, n, n), lambda x, y, z: W.tgv3d_points(x, y, z, n, cfg["u0"]), 3)
+    err = np.abs(got - want).max()
+    print("D3Q15 raw 512^3 %s three steps: max|d df| = %.3e" % (storage, err))
+    assert err <= 3 * tol
+
+
 def test_d3q27_cumulant_512_conservation_and_symmetry():
     """FP32, 20 steps at 512^3: mass and momentum stay at their initial sums and the velocity
     keeps the vortex's mirror symmetry u_x(-x) = -u_x(x), u_y(-x) = u_y(x)."""
