@@ -157,8 +157,9 @@ typedef enum { LBM_BASIS_GRADED = 0, LBM_BASIS_WEIGHTED_ORTHOGONAL = 1, LBM_BASI
 
 /* Device layout of the populations (x fastest in both).  PLANES: one plane per population,
  * [q][z][y][x] with a padded plane stride.  ROWS: the q populations of one row side by side,
- * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS, except
- * PLANES for F64 storage with AA streaming (the faster layout measured on MI355X). */
+ * [z][y][q][x], so the rows a block reads and writes are contiguous.  AUTO: ROWS (the faster
+ * layout measured on MI355X for every storage type and streaming pattern), or PLANES where one
+ * z-plane of the ROWS layout would reach 4 GiB. */
 typedef enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_PLANES = 1, LBM_LAYOUT_ROWS = 2 } lbm_layout;
 
 typedef struct {

@@ -41,10 +41,12 @@ size_t plane_elems(const lbm_params *p) {
 
 int resolve_layout(const lbm_params *p) {
   if (p->layout == LBM_LAYOUT_PLANES || p->layout == LBM_LAYOUT_ROWS) return p->layout;
-  // measured: rows for every storage with pull streaming and for F32/F16 with AA; F64 with AA
-  // streams faster from planes
-  const bool in_place = p->streaming != LBM_STREAM_PULL && p->streaming != LBM_STREAM_PUSH;
-  return (p->storage == LBM_STORE_F64 && in_place) ? LBM_LAYOUT_PLANES : LBM_LAYOUT_ROWS;
+  // measured: rows for every storage and streaming pattern under the autotuned launch; planes
+  // only where a rows z-plane (q padded rows per y) would not fit 32-bit lane offsets
+  const double align = 256.0 / double(storage_bytes(p->storage));
+  const double nxp = std::ceil(double(p->nx) / align) * align;
+  const double rows_plane = double(p->ny) * double(stencil_q(p->stencil)) * nxp * double(storage_bytes(p->storage));
+  return rows_plane >= 4294967295.0 ? LBM_LAYOUT_PLANES : LBM_LAYOUT_ROWS;
 }
 
 // element strides of population i, z and y (x has stride 1) and elements per buffer

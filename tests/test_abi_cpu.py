@@ -117,6 +117,11 @@ def test_layout_enum_checked_and_large_boxes_accepted():
         lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f32", streaming="pull"))
     # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
     assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
+    # a rows z-plane of 29 GiB is refused, but AUTO falls back to planes (1 GiB z-planes)
+    assert lbm.lbm_validate(_p(dims=(65536, 4096, 2), storage="f32", layout="rows")) == lbm.LBM_EUNSUPPORTED
+    assert lbm.lbm_validate(_p(dims=(65536, 4096, 2), storage="f32", layout="auto")) == 0
+    assert lbm.lbm_required_bytes(_p(dims=(65536, 4096, 2), storage="f32", layout="auto")) == \
+        lbm.lbm_required_bytes(_p(dims=(65536, 4096, 2), storage="f32", layout="planes"))
 
 
 def test_srt_and_literal_parameter_sets():
