@@ -972,14 +972,23 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   // the buffer that is restored afterwards and time their even and odd steps alternately, as
   // they run, over an even number of steps
   const bool two = two_buffers(c);
+  hipEvent_t e0, e1;
+  HIPCHECK(hipEventCreate(&e0), "event");
+  if (hipError_t ee = hipEventCreate(&e1); ee != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return hip_fail(ee, "event");
+  }
   void *saved = nullptr;
   if (!two) {
     hipError_t e = hipMalloc(&saved, c->buf_bytes);
+    if (e == hipSuccess) e = hipMemcpyAsync(saved, c->buf[0], c->buf_bytes, hipMemcpyDeviceToDevice, c->stream);
     if (e != hipSuccess) {
       (void)hipGetLastError();
+      if (saved) (void)hipFree(saved);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       return fail(LBM_ENOMEM, "autotuning the in-place pattern needs a temporary copy of the state");
     }
-    HIPCHECK(hipMemcpyAsync(saved, c->buf[0], c->buf_bytes, hipMemcpyDeviceToDevice, c->stream), "save state");
   }
   const int cur0 = c->cur;
   const int64_t t0 = c->t;
@@ -996,9 +1005,6 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   // best uncapped shape per block size (64, 128, 256, 512 threads), the starting points of phase 2
   double best_t[4] = {1e300, 1e300, 1e300, 1e300};
   std::array<int, 4> shape_t[4] = {};
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  HIPCHECK(hipEventCreate(&e1), "event");
   lbm_status st = LBM_OK;
   for (const auto &cd : cand) {
     c->bx = cd[0];
