@@ -6,7 +6,8 @@
   the identity) and omega = 2 (the zero-viscosity limit of eq. MrtUpdateGeneral).
 * lbm_step(0) changes nothing; lbm_step rejects a negative count.
 * The rest state (df = 0) and the shallow-water lake at rest are exact fixed points in every
-  precision (bit-exact zero after 50 steps).
+  precision (bit-exact zero after 50 steps); a uniform flow stays bit-identical across cells
+  and at its equilibrium.
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 5 steps from a non-equilibrium state.
 """
@@ -139,3 +140,33 @@ def test_lake_at_rest_is_an_exact_fixed_point(storage):
     lat.lbm_init_equilibrium(np.ones((1, 17, 33)), np.zeros((3, 1, 17, 33)))
     lat.lbm_step(50)
     assert not np.any(lat.lbm_get_populations())
+
+
+@pytest.mark.parametrize("space", ["raw", "central", "cumulant", "srt"])
+@pytest.mark.parametrize("storage,tol", [("f64", 5e-15), ("f32", 2e-6)])
+@pytest.mark.parametrize("streaming", ["pull", "aa", "twist", "push"])
+def test_uniform_flow_stays_uniform_and_at_equilibrium(space, storage, tol, streaming):
+    """A uniform flow (rho = 1.01, u = (0.05, -0.03, 0.02)) is the equilibrium everywhere, a
+    fixed point of every collision.  Every cell does the same arithmetic on the same inputs,
+    so after 50 steps all cells hold bit-identical populations (whatever the launch tiling
+    or streaming pattern), and those stay within rounding of the oracle's equilibrium.
+    Bars: the conserved moments do not relax, so their rounding can accumulate; at most
+    half an ulp of |df| <= 0.03 per population and step gives 50 * 27 * ulp / 2, about 2.4e-15
+    in FP64 and 1.3e-6 in FP32."""
+    st = O.stencil("D3Q27")
+    om = _general("D3Q27")
+    if space == "srt":
+        om[[j for j in range(st.q) if st.order(j) >= 2]] = 1.4
+    dims = (70, 9, 5)
+    nx, ny, nz = dims
+    u0 = np.array([0.05, -0.03, 0.02])
+    lat = lbm.Lattice("D3Q27", space, om, dims, storage=storage, streaming=streaming)
+    lat.lbm_init_equilibrium(np.full((nz, ny, nx), 1.01), np.broadcast_to(u0[:, None, None, None], (3, nz, ny, nx)).copy())
+    lat.lbm_step(50)
+    df = lat.lbm_get_populations().reshape(st.q, -1)
+    assert np.all(df == df[:, :1])
+    m = O.Method("D3Q27", space, om)
+    want = O.init_equilibrium(m, np.full((1, 1, 1), 1.01), u0[:, None, None, None]).reshape(st.q)
+    err = np.abs(df[:, 0] - want).max()
+    print("uniform flow %s %s %s: max|df - df_eq| = %.3e" % (space, storage, streaming, err))
+    assert err <= tol
