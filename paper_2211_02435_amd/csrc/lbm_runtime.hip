@@ -902,7 +902,8 @@ static std::string tune_key(const lbm_ctx *c) {
   std::ostringstream k;
   k << "s" << c->s << "_sp" << c->space << "_eq" << c->eq << "_r" << int(c->reg) << "_st" << c->store << "_pat"
     << c->pattern << "_lay" << c->layout << (c->literal ? "_lit" + std::to_string(c->form) : std::string())
-    << (c->p.zero_centered ? "" : "_abs") << "_" << c->nx << "x" << c->ny << "x" << c->nz;
+    << (c->p.zero_centered ? "" : "_abs") << (c->R.cross ? "_cross" : "") << (forced(c) ? "_force" : "") << "_"
+    << c->nx << "x" << c->ny << "x" << c->nz;
   return k.str();
 }
 
@@ -925,23 +926,34 @@ static bool cache_lookup(const std::string &file, const std::string &key, int *b
 
 static void cache_store(const std::string &file, const std::string &key, int bx, int by, int swz, int vec, int lds,
                         double ms) {
-  std::vector<std::string> lines;
+  // keep every other "key": [values] pair of the file, whatever its line layout
+  std::vector<std::pair<std::string, std::string>> kept;
   {
     std::ifstream in(file);
-    std::string line;
-    while (std::getline(in, line)) {
-      if (line.find('"') == std::string::npos) continue;
-      if (line.find("\"" + key + "\"") != std::string::npos) continue;
-      while (!line.empty() && (line.back() == ',' || line.back() == ' ')) line.pop_back();
-      lines.push_back(line);
+    std::ostringstream ss;
+    ss << in.rdbuf();
+    const std::string text = ss.str();
+    size_t p = 0;
+    for (;;) {
+      const size_t k0 = text.find('"', p);
+      if (k0 == std::string::npos) break;
+      const size_t k1 = text.find('"', k0 + 1);
+      if (k1 == std::string::npos) break;
+      const size_t lb = text.find('[', k1);
+      const size_t rb = lb == std::string::npos ? std::string::npos : text.find(']', lb);
+      if (rb == std::string::npos) break;
+      std::string k = text.substr(k0 + 1, k1 - k0 - 1);
+      if (k != key) kept.emplace_back(std::move(k), text.substr(lb, rb - lb + 1));
+      p = rb + 1;
     }
   }
-  char buf[256];
-  std::snprintf(buf, sizeof(buf), "  \"%s\": [%d, %d, %d, %d, %d, %.6f]", key.c_str(), bx, by, swz, vec, lds, ms);
-  lines.push_back(buf);
+  char buf[128];
+  std::snprintf(buf, sizeof(buf), "[%d, %d, %d, %d, %d, %.6f]", bx, by, swz, vec, lds, ms);
+  kept.emplace_back(key, buf);
   std::ofstream out(file, std::ios::trunc);
   out << "{\n";
-  for (size_t i = 0; i < lines.size(); ++i) out << lines[i] << (i + 1 < lines.size() ? ",\n" : "\n");
+  for (size_t i = 0; i < kept.size(); ++i)
+    out << "  \"" << kept[i].first << "\": " << kept[i].second << (i + 1 < kept.size() ? ",\n" : "\n");
   out << "}\n";
 }
 

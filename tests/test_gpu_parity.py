@@ -369,6 +369,43 @@ def test_occupancy_cap_and_autotune_leave_results_unchanged(streaming):
         lat.lbm_set_lds_reserve(65537)
 
 
+def test_autotune_cache_round_trip(tmp_path, monkeypatch):
+    """LBM_AUTOTUNE_CACHE: the first autotune writes the chosen launch under a key of the
+    method, precision, pattern, layout and size; a second context of the same configuration
+    takes it from the file; another configuration adds its own key and keeps the first."""
+    import json
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(cache))
+    dims = (70, 9, 5)
+    om = _rates("D3Q27", "reg")
+    rho, u = W.random_near_equilibrium_fields(dims[::-1], seed=9, drho=5e-3, umax=0.04)
+
+    def tuned(streaming="pull", basis="graded"):
+        lat = lbm.Lattice("D3Q27", "raw" if basis != "graded" else "cumulant", om, dims, storage="f32",
+                          streaming=streaming, basis=basis)
+        lat.lbm_init_equilibrium(rho, u)
+        lat.lbm_autotune()
+        return lat, list(lat.lbm_get_launch()) + [int(lat.lbm_get_vectorized()), lat.lbm_get_lds_reserve()]
+
+    a, la = tuned()
+    data = json.loads(cache.read_text())
+    assert len(data) == 1 and list(data.values())[0][:5] == la
+    # a hand-edited entry is what the next context of this configuration takes
+    key = list(data)[0]
+    edited = [64, 2, 0, 0, 26624]
+    cache.write_text(json.dumps({key: edited + [1.0]}))
+    b, lb = tuned()
+    assert lb == edited
+    a.lbm_step(3)
+    b.lbm_step(3)
+    np.testing.assert_array_equal(a.lbm_get_populations(), b.lbm_get_populations())
+    tuned("aa")
+    tuned("pull", "weighted_orthogonal")
+    data = json.loads(cache.read_text())
+    assert len(data) == 3 and data[key][:5] == edited
+    assert any("_cross" in k for k in data)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
 @pytest.mark.parametrize("streaming", ["pull", "aa"])
 @pytest.mark.parametrize("layout", ["planes", "rows"])
