@@ -66,9 +66,20 @@ def workload_rates(cfg, general=False):
     return om
 
 
+def apply_launch(lat, spec):
+    """Set a launch given as "bx,by,swizzle,variant,lds" (variant 0 per-cell, 1 vectorised,
+    2 LDS-staged)."""
+    bx, by, swz, var, lds = (int(v) for v in spec.split(","))
+    lat.lbm_set_launch(bx, by, swz)
+    lat.lbm_set_vectorized(var == 1)
+    lat.lbm_set_staged(var == 2)
+    lat.lbm_set_lds_reserve(lds)
+
+
 def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, streaming, layout, transform="chimera",
-                general=False):
-    """Run one box: init, autotune, warm-up, record the graph, time `steps` sweeps."""
+                general=False, launch=None):
+    """Run one box: init, autotune (or the given launch), warm-up, record the graph, time
+    `steps` sweeps."""
     import torch
     stencil, space = cfg["stencil"], cfg["space"]
     om = workload_rates(cfg, general)
@@ -78,7 +89,9 @@ def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, stream
         kw = {"equilibrium": "swe", "gravity": cfg["gravity"]}
     lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming, layout=layout, **kw)
     lat.lbm_init_equilibrium(*fields)
-    if autotune:
+    if launch:
+        apply_launch(lat, launch)
+    elif autotune:
         lat.lbm_autotune()
     if transform != "chimera":
         bx, by, _ = lat.lbm_get_launch()
@@ -100,8 +113,8 @@ def measure_box(lbm, cfg, storage, fields, dims, steps, warmup, autotune, stream
     res = {"mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
            "avg_launch_ms": t_launch * 1e3, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
            "bytes_per_lup": 2 * q * SBYTES[storage],
-           "launch_bx_by_swizzle_vec_lds": list(lat.lbm_get_launch()) + [int(lat.lbm_get_vectorized()),
-                                                                        lat.lbm_get_lds_reserve()],
+           "launch_bx_by_swizzle_variant_lds": list(lat.lbm_get_launch()) + [
+               1 if lat.lbm_get_vectorized() else (2 if lat.lbm_get_staged() else 0), lat.lbm_get_lds_reserve()],
            "transform": lat.lbm_get_transform(), "layout": lat.lbm_get_layout()}
     return lat, res
 
@@ -118,7 +131,6 @@ def measure_batch(lbm, steps, warmup):
     del fields
     bat = lbm.Batch("D3Q27", "central", dims, rates, storage="f32")
     bat.lbm_batch_init_equilibrium(rho, u)
-    del rho, u
     launch = bat.lbm_batch_autotune()
     bat.lbm_batch_step(warmup)
     bat.lbm_batch_graph_prepare(steps)
@@ -130,26 +142,161 @@ def measure_batch(lbm, steps, warmup):
     wall = time.perf_counter() - t0
     cells = bat.lbm_batch_cells()
     gbs = 216 * cells / (ms / 1e3 / steps) / 1e9
-    return {"boxes": len(boxes), "cells": cells, "steps": steps, "graph_steps": steps,
-            "mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
-            "avg_launch_ms": ms / steps, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
-            "storage": "f32", "space": "central", "launch_threads_swizzle_lds": list(launch)}
+    res = {"boxes": len(boxes), "cells": cells, "steps": steps, "graph_steps": steps,
+           "mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
+           "avg_launch_ms": ms / steps, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
+           "storage": "f32", "space": "central", "launch_threads_swizzle_lds": list(launch)}
+    res["vs_oracle"] = batch_accuracy(lbm, bat, boxes, dims, rho, u)
+    return res
 
 
-def cpu_baseline(cfg, n, steps):
-    """The FP64 oracle, single-threaded, on an n^3 copy of the Taylor-Green workload."""
-    from threadpoolctl import threadpool_limits
+def batch_accuracy(lbm, bat, boxes, dims, rho, u):
+    """Outside the timed region: the ensemble re-initialised and advanced by one replay of the
+    100-step graph; the velocity of its sampled edge-32 boxes against the FP64 oracle's values
+    at their sampled cells (tests/golden/ensemble32_oracle.npz, written from the oracle alone)."""
+    import torch
+    path = os.path.join(ROOT, "tests", "golden", "ensemble32_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    steps = int(ref["steps"])
+    bat.lbm_batch_init_equilibrium(rho, u)
+    bat.lbm_batch_graph_prepare(steps)
+    bat.lbm_batch_step(steps)
+    n = bat.lbm_batch_cells()
+    rg = torch.empty(n, dtype=torch.float64, device="cuda")
+    ug = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lbm.check(lbm.load().lbm_batch_macroscopic(bat.b, lbm._dptr(rg), lbm._dptr(ug)))
+    offs = np.concatenate([[0], np.cumsum([d[0] * d[1] * d[2] for d in dims])])
+    worst = 0.0
+    per_box = {}
+    for k in (int(v) for v in ref["boxes"]):
+        e = dims[k][0]
+        uk = ug[3 * int(offs[k]):3 * int(offs[k + 1])].view(3, e, e, e).cpu().numpy()
+        pts = ref["u_pts_%d" % k]
+        got = uk[:, pts[:, 2], pts[:, 1], pts[:, 0]].T
+        rel = float(np.linalg.norm(got - ref["u_%d" % k]) / np.linalg.norm(ref["u_%d" % k]))
+        per_box[str(k)] = rel
+        worst = max(worst, rel)
+    del rg, ug
+    torch.cuda.empty_cache()
+    return {"velocity_rel_l2_vs_oracle_max": worst, "per_box": per_box, "steps": steps,
+            "sample": "edge-32 boxes %s of the ensemble, %d sampled cells each, after one replay of the "
+                      "%d-step graph" % (list(per_box), len(ref["u_pts_%d" % int(ref["boxes"][0])]), steps)}
+
+
+def oracle_accuracy(lbm, cfg):
+    """Outside the timed region: the 128^3 copy of the metric workload (same u0 and rates) in
+    FP32 and FP64 against the FP64 oracle's values at sampled cells
+    (tests/golden/tgv128_cumulant_oracle.npz, written from the oracle alone): max |d df| after
+    100 steps and the relative L2 velocity error after 200 steps."""
+    path = os.path.join(ROOT, "tests", "golden", "tgv128_cumulant_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    n, u0, k1, k2 = int(ref["n"]), float(ref["u0"]), int(ref["df_step"]), int(ref["steps"])
+    fields = W.tgv3d_fields(n, u0=u0)
+    pts = ref["df_pts"]
+    zz, yy, xx = np.meshgrid(ref["z"], ref["y"], ref["x"], indexing="ij")
+    out = {"copy": "%d^3, u0 %.2f, omega_s %.6f" % (n, u0, cfg["omega_shear"]),
+           "df_step": k1, "velocity_step": k2, "df_cells": len(pts), "velocity_cells": int(zz.size)}
+    for st in ("f32", "f64"):
+        lat = lbm.Lattice(cfg["stencil"], cfg["space"], workload_rates(cfg), (n, n, n), storage=st)
+        lat.lbm_init_equilibrium(*fields)
+        lat.lbm_autotune()
+        lat.lbm_step(k1)
+        df = lat.lbm_get_populations()
+        err = float(np.abs(df[:, pts[:, 2], pts[:, 1], pts[:, 0]].T - ref["df"]).max())
+        del df
+        lat.lbm_step(k2 - k1)
+        _, ug = lat.lbm_macroscopic()
+        lat.close()
+        us = ug[:, zz, yy, xx]
+        out[st] = {"max_abs_df_vs_oracle": err,
+                   "velocity_rel_l2_vs_oracle": float(np.linalg.norm(us - ref["u"]) / np.linalg.norm(ref["u"]))}
+    return out
+
+
+_ORACLE_METHODS = {}
+
+
+def _oracle_method(spec):
     import oracle as O
-    with threadpool_limits(limits=1):
-        m = O.Method(cfg["stencil"], cfg["space"], O.regularized_rates(cfg["stencil"], cfg["omega_shear"]))
-        rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
-        df = O.init_equilibrium(m, rho, u)
+    if spec not in _ORACLE_METHODS:
+        stencil, space, omega = spec
+        _ORACLE_METHODS[spec] = O.Method(stencil, space, O.regularized_rates(stencil, omega))
+    return _ORACLE_METHODS[spec]
+
+
+def _oracle_collide_slab(args):
+    import oracle as O
+    spec, slab = args
+    return O.collide(_oracle_method(spec), slab)
+
+
+def _oracle_rate(spec, fields, steps, procs):
+    """Oracle MLUPS of `steps` steps from the equilibrium of `fields`: collide on `procs` slabs in
+    a process pool (procs > 1) or in this process, then stream; init is not timed."""
+    import oracle as O
+    m = _oracle_method(spec)
+    df = O.init_equilibrium(m, *fields)
+    cells = fields[0].size
+    axis = 1 if df.shape[1] > 1 else 2
+    if procs == 1:
         t0 = time.perf_counter()
         O.step(m, df, steps)
+        return cells * steps / (time.perf_counter() - t0) / 1e6
+    from multiprocessing import get_context
+    with get_context("fork").Pool(procs) as pool:
+        pool.map(_oracle_collide_slab, [(spec, s) for s in np.array_split(df[:, :procs], procs, axis=axis)])
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            slabs = np.array_split(df, procs, axis=axis)
+            df = O.stream(m, np.concatenate(pool.map(_oracle_collide_slab, [(spec, s) for s in slabs]), axis=axis))
         dt = time.perf_counter() - t0
-    return {"value": n ** 3 * steps / dt / 1e6, "unit": "MLUPS", "cores": 1, "kind": "oracle",
-            "sample": "FP64 numpy oracle (dense K(u), set-partition cumulants), %d^3 copy of the same "
-                      "Taylor-Green workload, %d steps, %.1f s" % (n, steps, dt)}
+    return cells * steps / dt / 1e6
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, n_all=128, steps_all=2, n_one=64, steps_one=2, d2q9_steps=250):
+    """The FP64 oracle on the host cores, before the GPU is touched (its process pool forks):
+    the D3Q27 cumulant Taylor-Green workload on a 128^3 copy with every usable core (one worker
+    process per core, at most 16) and on a 64^3 copy with one core, and the D2Q9 central-moment
+    64^2 Taylor-Green run (the small workload) with one core.  One BLAS thread per process."""
+    for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[v] = "1"
+    from threadpoolctl import threadpool_limits
+    cores = min(16, len(os.sched_getaffinity(0)))
+    spec = (cfg["stencil"], cfg["space"], cfg["omega_shear"])
+    c2 = W.WORKLOADS["d2q9_central_64"]
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        all_cores = _oracle_rate(spec, W.tgv3d_fields(n_all, u0=cfg["u0"]), steps_all, cores)
+        one_core = _oracle_rate(spec, W.tgv3d_fields(n_one, u0=cfg["u0"]), steps_one, 1)
+        d2q9 = _oracle_rate((c2["stencil"], c2["space"], c2["omega_shear"]),
+                            W.tgv2d_fields(64, 64, 1, u0=c2["u0"]), d2q9_steps, 1)
+    wall = time.perf_counter() - t0
+    return {"value": all_cores, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": "FP64 numpy oracle (dense K(u), set-partition cumulants) on the D3Q27 cumulant "
+                      "Taylor-Green workload: %d^3 copy, %d steps, %d worker processes; %.1f s for all "
+                      "three legs" % (n_all, steps_all, cores, wall),
+            "single_core": {"value": one_core, "unit": "MLUPS", "cores": 1,
+                            "sample": "%d^3 copy, %d steps" % (n_one, steps_one)},
+            "d2q9_central_64": {"value": d2q9, "unit": "MLUPS", "cores": 1,
+                                "sample": "D2Q9 central-moment 64^2 Taylor-Green (u0 0.01, omega_s 1.6), "
+                                          "%d of its 1000 steps" % d2q9_steps},
+            "nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0)), "cpu_model": _cpu_model()}
 
 
 def copy_ceiling(lbm):
@@ -194,8 +341,12 @@ def main():
                     help="general: every rate of order >= 3 set to 1.3 (non-regularized kernels)")
     ap.add_argument("--transform", default="chimera", choices=["chimera", "dense_mfma"],
                     help="dense_mfma: the measured ablation of the raw-moment transform on MFMA")
-    ap.add_argument("--cpu-size", type=int, default=32)
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--launch", default=None,
+                    help="bx,by,swizzle,variant,lds for every storage instead of autotuning (variant 0 "
+                         "per-cell, 1 vectorised, 2 LDS-staged)")
+    ap.add_argument("--fp64-launch", default=None, help="the same for the FP64 run (default: --launch)")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the checks against the oracle's reference values (outside the timed region)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -203,11 +354,19 @@ def main():
               "as z-slabs with one halo exchange per step; not built).", file=sys.stderr)
         sys.exit(2)
 
+    name = args.workload
+    cfg = W.WORKLOADS[name]
+    n = args.size or cfg.get("dims", (0,))[0]
+    is_metric = name == "d3q27_cumulant_512" and n == cfg["dims"][0]
+    cpu = None
+    if is_metric and not args.no_cpu:
+        # before the GPU is touched: the oracle's worker processes are forked
+        print("[bench] cpu baseline (FP64 oracle)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cfg)
+
     import torch
     from paper_2211_02435_amd import lbm
 
-    name = args.workload
-    cfg = W.WORKLOADS[name]
     if name == "batch_d3q27_central":
         res = measure_batch(lbm, args.steps, args.warmup)
         out = {"metric": "MLUPS and % of HBM roofline, batched ensemble of 256 D3Q27 central-moment boxes",
@@ -220,7 +379,6 @@ def main():
         print(json.dumps(out), flush=True)
         return
 
-    n = args.size or cfg["dims"][0]
     fields, dims = workload_fields(name, cfg, n)
     storages = {"swe_d2q9_4096": ["f16", "f64"], "d2q9_central_64": ["f64"]}.get(name, ["f32", "f64"])
     if args.no_fp64:
@@ -229,9 +387,10 @@ def main():
           file=sys.stderr, flush=True)
     runs, lats = {}, {}
     for st in storages:
+        launch = (args.fp64_launch or args.launch) if st == "f64" else args.launch
         lat, res = measure_box(lbm, cfg, st, fields, dims, args.steps, args.warmup,
                                not args.no_autotune, args.streaming, args.layout, args.transform,
-                               args.rates == "general")
+                               args.rates == "general", launch)
         runs[st], lats[st] = res, lat
         print("[bench] %s: %.0f MLUPS, %.1f GB/s" % (st, res["mlups"], res["achieved_GBps"]),
               file=sys.stderr, flush=True)
@@ -245,15 +404,15 @@ def main():
     lats.clear()
     torch.cuda.empty_cache()
 
-    is_metric = name == "d3q27_cumulant_512" and n == cfg["dims"][0]
     batch = None
     if is_metric and not args.no_batch:
         batch = measure_batch(lbm, 100, args.warmup)
         print("[bench] batch: %.0f MLUPS" % batch["mlups"], file=sys.stderr, flush=True)
     ceiling = copy_ceiling(lbm)
-    cpu = None
-    if is_metric and not args.no_cpu:
-        cpu = cpu_baseline(cfg, args.cpu_size, args.cpu_steps)
+    accuracy = None
+    if is_metric and not args.no_accuracy:
+        accuracy = oracle_accuracy(lbm, cfg)
+        print("[bench] accuracy vs oracle: %s" % json.dumps(accuracy), file=sys.stderr, flush=True)
 
     r = runs[main_st]
     fields_desc = ("shallow water g 0.1, 16 Gaussian bumps" if name == "swe_d2q9_4096"
@@ -278,7 +437,7 @@ def main():
         "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
                    "layout": r.get("layout", args.layout), "streaming": args.streaming, "transform": args.transform,
                    "rates": args.rates,
-                   "launch_bx_by_swizzle_vec_lds": r["launch_bx_by_swizzle_vec_lds"]},
+                   "launch_bx_by_swizzle_variant_lds": r["launch_bx_by_swizzle_variant_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
                      "traffic": measured_traffic(name, r.get("layout")) if (n == cfg["dims"][0] and main_st == "f32"
@@ -290,6 +449,7 @@ def main():
                      "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},
         "fp64": runs.get("f64") if main_st != "f64" else None,
         "velocity_rel_l2_vs_fp64": vel,
+        "vs_oracle_128_copy": accuracy,
         "batched": batch,
         "copy_ceiling_GBps": ceiling,
         "cpu_baseline": cpu,

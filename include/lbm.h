@@ -176,6 +176,7 @@ typedef struct {
   int storage;            /* lbm_storage                                                      */
   int streaming;          /* lbm_streaming                                                    */
   void *buffers[2];       /* optional caller-owned device buffers (e.g. torch allocations);   */
+                          /* LBM_EINVAL from lbm_create if one is not device memory          */
   size_t buffer_bytes;    /* each >= lbm_required_bytes / nbuffers; NULL -> library allocates */
   void *stream;           /* hipStream_t to run on; NULL -> the library creates its own       */
   int layout;             /* lbm_layout of the device population buffers                      */
@@ -231,11 +232,13 @@ void lbm_destroy(lbm_ctx *ctx);
 lbm_status lbm_init_equilibrium(lbm_ctx *ctx, const double *rho, const double *u);
 
 /* Advance n >= 0 time steps (fused collide + stream).  Asynchronous on the context stream.
- * With graphs enabled (default) the n launches are recorded once into a hipGraph per
- * (n, buffer parity) and replayed. */
+ * With graphs enabled (default) the launches are recorded once into hipGraphs of at most 256
+ * steps per (length, buffer parity) and replayed: n / 256 replays of the 256-step graph, then
+ * a graph of the remainder (a single remaining step runs directly).  At most 8 graphs are
+ * kept per context; recording another one first drops them all. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
-/* Record (without running) the hipGraph that the next lbm_step(n) will replay, so that the
+/* Record (without running) the hipGraphs that the next lbm_step(n) will replay, so that the
  * recording cost stays out of a timed region.  No effect for n < 2 or with graphs off. */
 lbm_status lbm_graph_prepare(lbm_ctx *ctx, int64_t n);
 
@@ -274,17 +277,36 @@ lbm_status lbm_set_time(lbm_ctx *ctx, int64_t t);
 
 /* Launch shape of the sweep: block of bx * by threads covering bx cells along x and by rows
  * along y; xcd_swizzle != 0 maps consecutive tiles to the same XCD.  bx * by must be a
- * multiple of 64 and <= 1024. */
+ * multiple of 64 and <= 512. */
 lbm_status lbm_set_launch(lbm_ctx *ctx, int bx, int by, int xcd_swizzle);
 lbm_status lbm_get_launch(const lbm_ctx *ctx, int *bx, int *by, int *xcd_swizzle);
 
 /* Vectorised sweep: each lane owns V x-adjacent cells (V = 2 for F64/F32, 4 for F16) and reads
  * each population row segment with one aligned vector load, the x +- 1 neighbours coming from
  * the adjacent lane (wave shift).  Needs nx to be a multiple of bx * V (LBM_EUNSUPPORTED
- * otherwise); AA odd steps always use the per-cell kernel.  Off by default; lbm_autotune
+ * otherwise); AA odd steps use the per-cell kernel (or the LDS-shifted one, lbm_set_staged).
+ * Off by default; lbm_autotune
  * considers it. */
 lbm_status lbm_set_vectorized(lbm_ctx *ctx, int enable);
 int lbm_get_vectorized(const lbm_ctx *ctx);
+/* LDS variants of the streaming patterns of sec. 4.4 (eq. LbUpdateScheme).
+ * Pull: the LDS-staged sweep.  Each block of bx x 1 threads (bx = 128 or 256) owns bx
+ * consecutive cells of one row; it first copies the q source row segments it gathers from
+ * (cells x0 - E .. x0 + bx + E - 1 of population i in row (y - cy, z - cz), E elements per
+ * 16-byte chunk) from HBM into LDS with 16-byte global-to-LDS loads, then each thread reads its
+ * q values from LDS, collides and stores.  Needs by = 1, bx in {128, 256}, nx a multiple of bx
+ * and 16-byte aligned population rows.
+ * AA: the odd step (which writes slot i at x + xi) puts the post-collision values of the
+ * populations with cx != 0 into LDS and stores each row segment of the block aligned, the
+ * value of the cell one to the left or right on every position; only the two block ends write
+ * single elements.  Needs at most 256 threads per block and nx a multiple of bx.  Even steps
+ * use the per-cell kernel.
+ * LBM_EUNSUPPORTED for other shapes or patterns; a later lbm_set_launch with a shape the
+ * variant cannot run turns it off.  The forced, literal, orthogonal-basis and MFMA kernels
+ * ignore it.  Off by default; lbm_autotune considers it.  Results equal the register
+ * kernels' bit for bit. */
+lbm_status lbm_set_staged(lbm_ctx *ctx, int enable);
+int lbm_get_staged(const lbm_ctx *ctx);
 
 /* Collision-space transform of the sweep.  CHIMERA (default): the raw-moment Chimera passes
  * of sec. 4.1.1 in registers.  DENSE_MFMA (measured ablation): m = M df and df* = M^-1 dm* as
@@ -299,17 +321,20 @@ int lbm_get_transform(const lbm_ctx *ctx);
  * or -1 for a NULL context. */
 int lbm_get_layout(const lbm_ctx *ctx);
 
-/* Dynamic LDS reserved by every sweep block (0 .. 65536 bytes; the sweep itself uses none):
- * caps the resident blocks per CU (160 KB of LDS each), i.e. the number of waves streaming
- * concurrently.  0 by default; lbm_autotune considers it. */
+/* Dynamic LDS reserved by every sweep block (0 .. 65536 bytes; the register sweeps use none,
+ * the LDS-staged sweep takes the larger of the reserve and its own image): caps the resident
+ * blocks per CU (160 KB of LDS each), i.e. the number of waves streaming concurrently.  0 by
+ * default; lbm_autotune considers it. */
 lbm_status lbm_set_lds_reserve(lbm_ctx *ctx, int bytes);
 int lbm_get_lds_reserve(const lbm_ctx *ctx);
 
-/* Time candidate launch shapes (block shape, XCD swizzle, vectorised or per-cell kernel, then
- * the LDS reserve of the best shape) on
+/* Time candidate launch shapes (block shape, XCD swizzle, per-cell, vectorised or LDS-staged
+ * kernel, then the LDS reserve of the best shape of each block size) on
  * the context's own buffers (state is left unchanged) and keep the fastest; results are
- * cached per (method, precision, pattern, layout, size) in the JSON file named by
- * LBM_AUTOTUNE_CACHE, if set. */
+ * cached per (method, precision, pattern, layout, size, transform) in the JSON file named by
+ * LBM_AUTOTUNE_CACHE, if set.  With the MFMA transform only blocks of at most 256 threads,
+ * the per-cell kernel and no LDS reserve are considered.  Every return path restores the
+ * state, the step counter and (on failure) the previous launch. */
 lbm_status lbm_autotune(lbm_ctx *ctx);
 
 /* Enable (1) or disable (0) hipGraph recording in lbm_step. */
@@ -343,6 +368,8 @@ lbm_status lbm_batch_create(const lbm_params *common, int nboxes, const int64_t 
                             const double *omegas, lbm_batch **out);
 void lbm_batch_destroy(lbm_batch *b);
 lbm_status lbm_batch_init_equilibrium(lbm_batch *b, const double *rho, const double *u);
+/* n >= 0 steps of every box, one launch per step; graphs as for lbm_step (chunks of at most
+ * 256 steps, at most 8 graphs kept).  Asynchronous on the batch stream. */
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_graph_prepare(lbm_batch *b, int64_t n);
 lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u);

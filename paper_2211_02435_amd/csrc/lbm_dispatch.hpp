@@ -8,6 +8,8 @@ template <int S, int STORE>
 struct KTable {
   static const void *sweep(int sp, int eq, int reg, int pat);
   static const void *sweepv(int sp, int eq, int reg, int pat);
+  static const void *sweepl(int sp, int eq, int reg, int tw);
+  static const void *sweep_aa_shift(int sp, int eq, int reg);
   static const void *sweep_mfma(int sp, int reg);
   static const void *sweep_literal(int sp, int form);
   static const void *sweep_literal_cross(int form);
@@ -23,6 +25,9 @@ struct KTable {
 
 const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat);
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat);
+const void *sweepl_fn(int s, int store, int sp, int eq, int reg, int tw);
+int sweepl_lds_bytes(int s, int store, int tw);
+const void *sweep_aa_shift_fn(int s, int store, int sp, int eq, int reg);
 const void *sweep_mfma_fn(int s, int store, int sp, int reg);
 const void *sweep_literal_fn(int s, int store, int sp, int form);
 const void *sweep_literal_cross_fn(int s, int store, int form);

@@ -378,6 +378,180 @@ __global__ void __launch_bounds__(256) sweepv_kernel(SweepArgs<ST, CT> a) {
 }
 
 // ---------------------------------------------------------------------------------------
+// LDS-staged pull sweep: a block of TW threads owns TW consecutive cells of one row
+// (x0 .. x0 + TW - 1, with nx % TW == 0).  It first copies the Q source row segments it
+// gathers from, [x0 - E, x0 + TW + E) of population i in row (y - cy, z - cz), where E is the
+// number of elements in one 16-byte chunk, straight from HBM into LDS with gfx950's
+// global-to-LDS loads (16 bytes per lane, no register round trip; each wave's load fills
+// 64 consecutive chunks of LDS), waits for them, and then every thread reads its Q values
+// from LDS at x - cx, collides in registers and stores its populations like the register
+// kernel.  The LDS image of the block holds Q segments of SEG = TW / E + 2 chunks each.
+// ---------------------------------------------------------------------------------------
+template <int S>
+struct DirCode {
+  // (cx + 1) | (cy + 1) << 2 | (cz + 1) << 4 of population i, ten populations per word
+  static constexpr uint64_t word(int w) {
+    uint64_t v = 0;
+    for (int k = 0; k < 10; ++k) {
+      const int i = w * 10 + k;
+      if (i < Lat<S>::Q) {
+        const uint64_t code = uint64_t(Lat<S>::c(i, 0) + 1) | (uint64_t(Lat<S>::c(i, 1) + 1) << 2) |
+                              (uint64_t(Lat<S>::c(i, 2) + 1) << 4);
+        v |= code << (6 * k);
+      }
+    }
+    return v;
+  }
+  __device__ static __forceinline__ uint32_t of(uint32_t i) {
+    constexpr uint64_t w0 = word(0), w1 = word(1), w2 = word(2);
+    const uint32_t w = i / 10u, k = i - w * 10u;
+    const uint64_t v = w == 0 ? w0 : (w == 1 ? w1 : w2);
+    return uint32_t(v >> (6u * k)) & 63u;
+  }
+};
+
+template <class ST, int TW>
+struct StageGeom {
+  static constexpr int E = 16 / int(sizeof(ST));  // elements per 16-byte chunk
+  static constexpr int SEG = TW / E + 2;          // chunks per population segment
+};
+
+template <int S, class ST, int TW>
+constexpr int stage_lds_bytes() {
+  return Lat<S>::Q * StageGeom<ST, TW>::SEG * 16;
+}
+
+template <int S, int SP, int EQ, bool REG, class ST, class CT, int TW>
+__global__ void __launch_bounds__(TW) sweepl_kernel(SweepArgs<ST, CT> a) {
+  using L = Lat<S>;
+  constexpr int E = StageGeom<ST, TW>::E;
+  constexpr int SEG = StageGeom<ST, TW>::SEG;
+  constexpr int NCH = L::Q * SEG;
+  constexpr int ROUNDS = (NCH + TW - 1) / TW;
+  extern __shared__ __attribute__((aligned(16))) unsigned char stage_lds[];
+  const CellPos p = tile_cell_args(a, 1);  // bx == TW, by == 1: whole tiles, p.valid everywhere
+  const uint32_t t = threadIdx.x;
+  const uint32_t x0 = uint32_t(p.x) - t;
+  const Nbr<L::D> nb(p.x, p.y, p.z, a.nx, a.ny, a.nz, a.L);
+  const uint32_t xl = x0 == 0 ? uint32_t(a.nx - E) : x0 - E;            // left chunk (wrapped)
+  const uint32_t xr = x0 + TW == uint32_t(a.nx) ? 0u : x0 + TW;          // right chunk (wrapped)
+  const uint32_t wave_chunk0 = (t & ~63u);
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const uint32_t cw = uint32_t(r * TW) + wave_chunk0;  // first chunk of this wave's load
+    if (cw >= uint32_t(NCH)) break;                      // wave-uniform
+    const uint32_t c = cw + (t & 63u);
+    if (c < uint32_t(NCH)) {
+      const uint32_t i = c / uint32_t(SEG), k = c - i * uint32_t(SEG);
+      const uint32_t code = DirCode<S>::of(i);
+      const int cx = int(code & 3u) - 1, cy = int((code >> 2) & 3u) - 1, cz = int((code >> 4) & 3u) - 1;
+      (void)cx;
+      const uint32_t xe = k == 0 ? xl : (k == uint32_t(SEG - 1) ? xr : x0 + (k - 1) * uint32_t(E));
+      const ST *g = a.src + (uint64_t(i) * a.L.ps + nb.zpart(cz, -1)) + (nb.yoff[1 - cy] + xe);
+      // address-space conversions (flat -> global, flat -> LDS) need C-style casts
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(g),
+                                       (__attribute__((address_space(3))) void *)(stage_lds + size_t(cw) * 16u),
+                                       16, 0, 0);
+    }
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+
+  const ST *ls = reinterpret_cast<const ST *>(stage_lds);
+  CT g[L::G];
+  sfor<L::G>([&](auto K) { g[K] = CT(0); });
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0);
+    g[L::gidx(i)] = CT(ls[i * SEG * E + E - cx + int(t)]);
+  });
+  if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
+  collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+  if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(0, 1), nb.lane(0, 0, 1), ST(g[L::gidx(i)]));
+  });
+}
+
+// ---------------------------------------------------------------------------------------
+// AA odd step with LDS-shifted stores.  The odd step writes slot i at x + xi, one element off
+// the row alignment for cx != 0, so every wave of the per-cell kernel writes two partial
+// cache lines per shifted population.  Here a block (bx x by threads, whole tiles along x,
+// nx % bx == 0) first puts the post-collision values of its shifted populations into LDS,
+// then each thread stores position x0 + tx of a row segment with the value of cell
+// x0 + tx - cx, so the block writes whole lines except at its two ends: position x0 (cx = +1)
+// or x0 + bx - 1 (cx = -1) is left to the neighbouring block, and the edge thread stores its
+// own value beyond the block at x0 + bx or x0 - 1 (wrapped).  Every location is still read
+// and written by the block of the cell that owns it (reads before the barrier, writes after),
+// so the in-place step stays race-free.
+// ---------------------------------------------------------------------------------------
+template <int S>
+constexpr int n_shifted() {
+  int n = 0;
+  for (int i = 0; i < Lat<S>::Q; ++i) n += Lat<S>::c(i, 0) != 0;
+  return n;
+}
+template <int S>
+constexpr int shifted_index(int i) {  // rank of population i among those with cx != 0
+  int n = 0;
+  for (int j = 0; j < i; ++j) n += Lat<S>::c(j, 0) != 0;
+  return n;
+}
+
+template <int S, int SP, int EQ, bool REG, class ST, class CT>
+__global__ void __launch_bounds__(256) sweep_aa_odd_shift_kernel(SweepArgs<ST, CT> a) {
+  using L = Lat<S>;
+  extern __shared__ __attribute__((aligned(16))) unsigned char shift_lds[];
+  ST *sh = reinterpret_cast<ST *>(shift_lds);  // [n_shifted][by][bx]
+  const CellPos p = tile_cell_args(a, 1);      // p.x < nx always (whole tiles along x)
+  const int bx = a.bx, nthreads = a.bx * a.by;
+  const int tx = int(threadIdx.x), tid = int(threadIdx.y) * bx + tx;
+  const Nbr<L::D> nb(p.x, p.valid ? p.y : 0, p.z, a.nx, a.ny, a.nz, a.L);
+  CT g[L::G];
+  sfor<L::G>([&](auto E) { g[E] = CT(0); });
+  if (p.valid) {
+    sfor<L::Q>([&](auto I) {
+      constexpr int i = decltype(I)::value;
+      constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+      g[L::gidx(i)] = CT(ldp(a.src, (uint64_t(L::opp(i)) * a.L.ps) + nb.zpart(cz, -1), nb.lane(cx, cy, -1)));
+    });
+    if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] -= CT(L::w(I)); });
+    collide<S, SP, EQ, REG, CT>(g, a.R, a.grav);
+    if (a.absolute) sfor<L::Q>([&](auto I) { g[L::gidx(I)] += CT(L::w(I)); });
+  }
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+    const ST v = ST(g[L::gidx(i)]);
+    if constexpr (cx == 0) {
+      if (p.valid) stp(a.dst, (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1), nb.lane(0, cy, +1), v);
+    } else {
+      sh[shifted_index<S>(i) * nthreads + tid] = v;
+    }
+  });
+  __syncthreads();
+  if (!p.valid) return;
+  const uint32_t xo = uint32_t(p.x);
+  const uint32_t x_lo = xo == 0 ? uint32_t(a.nx - 1) : xo - 1;          // x - 1, wrapped
+  const uint32_t x_hi = xo + 1 == uint32_t(a.nx) ? 0u : xo + 1;          // x + 1, wrapped
+  sfor<L::Q>([&](auto I) {
+    constexpr int i = decltype(I)::value;
+    constexpr int cx = L::c(i, 0), cy = L::c(i, 1), cz = L::c(i, 2);
+    if constexpr (cx != 0) {
+      const uint64_t uni = (uint64_t(i) * a.L.ps) + nb.zpart(cz, +1);
+      const uint32_t row = nb.yoff[1 + cy];
+      const ST *shi = sh + shifted_index<S>(i) * nthreads + (tid - tx);
+      const int src_tx = tx - cx;  // the cell whose value lands on this thread's position
+      if (src_tx >= 0 && src_tx < bx) stp(a.dst, uni, row + xo, shi[src_tx]);
+      // the edge value that leaves the block
+      if (cx == 1 && tx == bx - 1) stp(a.dst, uni, row + x_hi, shi[tx]);
+      if (cx == -1 && tx == 0) stp(a.dst, uni, row + x_lo, shi[tx]);
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------------------
 // readers / writers of the canonical state
 // ---------------------------------------------------------------------------------------
 struct FieldArgs {

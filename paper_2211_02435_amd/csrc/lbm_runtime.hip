@@ -47,6 +47,16 @@ namespace lbm {
 
 const void *sweep_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweep, sp, eq, reg, pat) }
 const void *sweepv_fn(int s, int store, int sp, int eq, int reg, int pat) { LBM_TABLE_CALL(sweepv, sp, eq, reg, pat) }
+const void *sweepl_fn(int s, int store, int sp, int eq, int reg, int tw) { LBM_TABLE_CALL(sweepl, sp, eq, reg, tw) }
+// LDS image of sweepl_kernel: Q segments of StageGeom<ST, TW>::SEG 16-byte chunks
+int sweepl_lds_bytes(int s, int store, int tw) {
+  const int q = s == D2Q9 ? 9 : (s == D3Q19 ? 19 : (s == D3Q15 ? 15 : 27));
+  const int e = store == F64 ? 2 : (store == F32 ? 4 : 8);
+  return q * (tw / e + 2) * 16;
+}
+const void *sweep_aa_shift_fn(int s, int store, int sp, int eq, int reg) { LBM_TABLE_CALL(sweep_aa_shift, sp, eq, reg) }
+static_assert(stage_lds_bytes<D3Q27, float, 256>() == 27 * (256 / 4 + 2) * 16, "staged LDS image");
+static_assert(stage_lds_bytes<D3Q19, double, 128>() == 19 * (128 / 2 + 2) * 16, "staged LDS image");
 const void *sweep_mfma_fn(int s, int store, int sp, int reg) { LBM_TABLE_CALL(sweep_mfma, sp, reg) }
 const void *sweep_literal_fn(int s, int store, int sp, int form) { LBM_TABLE_CALL(sweep_literal, sp, form) }
 const void *sweep_literal_cross_fn(int s, int store, int form) { LBM_TABLE_CALL(sweep_literal_cross, form) }
@@ -105,6 +115,29 @@ static bool is_device_ptr(const void *p) {
   return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
 }
 
+// Two HIP events released on every return path of the timing helpers.
+struct EventPair {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  EventPair() = default;
+  EventPair(const EventPair &) = delete;
+  EventPair &operator=(const EventPair &) = delete;
+  ~EventPair() {
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  }
+  hipError_t create() {
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    return e;
+  }
+  // elapsed milliseconds between e0 and e1 (after waiting for e1)
+  hipError_t elapsed(float *ms) {
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+  }
+};
+
 }  // namespace lbm
 
 using namespace lbm;
@@ -130,6 +163,7 @@ struct lbm_ctx {
   bool own_stream = false;
   int bx = 64, by = 4, swz = 0;
   bool vec = false;   // vectorised sweep (V cells per lane) where the shape allows it
+  bool stage = false; // LDS-staged pull sweep where the shape allows it
   int lds = 0;        // dynamic LDS reserved per sweep block: caps resident blocks per CU
   int transform = 0;  // LBM_TRANSFORM_CHIMERA or LBM_TRANSFORM_DENSE_MFMA (ablation)
   bool literal = false;  // LBM_ARITH_LITERAL: the collision form evaluated as written
@@ -159,6 +193,32 @@ static uint32_t xcd_tile_host(uint32_t b, uint32_t n) {
   const uint32_t per = n / 8u, rem = n % 8u;
   const uint32_t xcd = b % 8u, local = b / 8u;
   return xcd < rem ? xcd * (per + 1u) + local : rem * (per + 1u) + (xcd - rem) * per + local;
+}
+
+// populations with cx != 0 (the ones the AA odd step writes one element off the alignment)
+static int n_shifted_pops(int s) {
+  switch (s) {
+    case D2Q9: return n_shifted<D2Q9>();
+    case D3Q19: return n_shifted<D3Q19>();
+    case D3Q15: return n_shifted<D3Q15>();
+  }
+  return n_shifted<D3Q27>();
+}
+static int aa_shift_lds_bytes(const lbm_ctx *c, int bx, int by) {
+  return n_shifted_pops(c->s) * bx * by * int(c->elem);
+}
+
+// The LDS variant of the pattern: pull -> the LDS-staged sweep (one row of 128 or 256 cells
+// per block, whole tiles along x, 16-byte aligned rows for the 16-byte global-to-LDS loads);
+// AA -> the odd step with LDS-shifted stores (at most 256 threads, whole tiles along x).
+static bool stage_ok(const lbm_ctx *c, int bx, int by) {
+  if (c->pattern == LBM_STREAM_AA)
+    return bx * by <= 256 && c->nx % bx == 0 && aa_shift_lds_bytes(c, bx, by) <= 65536;
+  if (c->pattern != LBM_STREAM_PULL) return false;
+  if (by != 1 || (bx != 128 && bx != 256) || c->nx % bx != 0) return false;
+  for (int k = 0; k < c->nbuf; ++k)
+    if (reinterpret_cast<uintptr_t>(c->buf[k]) % 16 != 0) return false;
+  return (c->L.ps * c->elem) % 16 == 0 && (c->L.zs * c->elem) % 16 == 0 && (uint64_t(c->L.ys) * c->elem) % 16 == 0;
 }
 
 static bool forced(const lbm_ctx *c) {
@@ -355,6 +415,16 @@ static lbm_status one_step(lbm_ctx *c, int sp_override = -1) {
     const void *fn = sweep_cross_fn(c->s, c->store, pat);
     if (!fn) return fail(LBM_EUNSUPPORTED, "no cross-order kernel for this stencil");
     HIPCHECK(launch_sweep(c, fn, src, dst, false), "sweep launch");
+  } else if (c->stage && pat == PULL && stage_ok(c, c->bx, c->by)) {
+    const void *fn = sweepl_fn(c->s, c->store, sp, eq, reg, c->bx);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no LDS-staged sweep kernel for this method");
+    const int lds = std::max(c->lds, sweepl_lds_bytes(c->s, c->store, c->bx));
+    HIPCHECK(launch_sweep_lds(c, fn, src, dst, lds), "sweep launch");
+  } else if (c->stage && pat == AA_ODD && stage_ok(c, c->bx, c->by)) {
+    const void *fn = sweep_aa_shift_fn(c->s, c->store, sp, eq, reg);
+    if (!fn) return fail(LBM_EUNSUPPORTED, "no LDS-shifted AA kernel for this method");
+    const int lds = std::max(c->lds, aa_shift_lds_bytes(c, c->bx, c->by));
+    HIPCHECK(launch_sweep_lds(c, fn, src, dst, lds), "sweep launch");
   } else {
     const bool vec = c->vec && (pat == PULL || pat == AA_EVEN) && vec_ok(c, c->bx);
     const void *fn = vec ? sweepv_fn(c->s, c->store, sp, eq, reg, pat) : sweep_fn(c->s, c->store, sp, eq, reg, pat);
@@ -473,6 +543,10 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   }
   for (int k = 0; k < c->nbuf; ++k) {
     if (p->buffers[k]) {
+      if (!is_device_ptr(p->buffers[k])) {
+        delete c;
+        return fail(LBM_EINVAL, "caller buffer " + std::to_string(k) + " is not device memory");
+      }
       if (p->buffer_bytes < c->buf_bytes) {
         delete c;
         return fail(LBM_ENOMEM, "caller buffer smaller than q * ncells * sizeof(storage)");
@@ -560,12 +634,23 @@ extern "C" lbm_status lbm_init_equilibrium(lbm_ctx *c, const double *rho, const 
 }
 
 namespace lbm {
+// Time loops are recorded in chunks of at most GRAPH_CHUNK steps (even, so a chunk keeps the
+// buffer parity); lbm_step(n) replays the chunk graph n / GRAPH_CHUNK times and a graph of the
+// remainder.  At most GRAPH_CACHE_MAX graphs are kept per context or batch; recording one more
+// drops them all.
+static const int64_t GRAPH_CHUNK = 256;
+static const size_t GRAPH_CACHE_MAX = 8;
+
 // the cached hipGraph that replays n sweeps from the current buffer parity (recorded once)
 static lbm_status graph_for(lbm_ctx *c, int64_t n, hipGraphExec_t *out) {
   const int parity = two_buffers(c) ? c->cur : int(c->t % 2);
   auto key = std::make_pair(n, parity);
   auto it = c->gcache.find(key);
   if (it == c->gcache.end()) {
+    if (c->gcache.size() >= GRAPH_CACHE_MAX) {
+      HIPCHECK(hipStreamSynchronize(c->stream), "sync before graph eviction");
+      clear_graphs(c);
+    }
     const int cur0 = c->cur;
     const int64_t t0 = c->t;
     lbm_status st = ensure_tiles(c);
@@ -606,20 +691,32 @@ extern "C" lbm_status lbm_step(lbm_ctx *c, int64_t n) {
     }
     return LBM_OK;
   }
-  hipGraphExec_t ex = nullptr;
-  lbm_status s = graph_for(c, n, &ex);
-  if (s != LBM_OK) return s;
-  HIPCHECK(hipGraphLaunch(ex, c->stream), "graph launch");
-  if (two_buffers(c)) c->cur ^= int(n & 1);
-  c->t += n;
+  while (n >= 2) {
+    const int64_t m = std::min(n, GRAPH_CHUNK);
+    hipGraphExec_t ex = nullptr;
+    lbm_status s = graph_for(c, m, &ex);
+    if (s != LBM_OK) return s;
+    HIPCHECK(hipGraphLaunch(ex, c->stream), "graph launch");
+    if (two_buffers(c)) c->cur ^= int(m & 1);
+    c->t += m;
+    n -= m;
+  }
+  if (n == 1) {
+    lbm_status st = ensure_tiles(c);
+    if (st == LBM_OK) st = one_step(c);
+    return st;
+  }
   return LBM_OK;
 }
 
 extern "C" lbm_status lbm_graph_prepare(lbm_ctx *c, int64_t n) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   if (n < 2 || !c->graphs) return LBM_OK;
+  // the chunk graph and the remainder graph (chunks are even: same parity)
   hipGraphExec_t ex = nullptr;
-  return graph_for(c, n, &ex);
+  lbm_status s = graph_for(c, std::min(n, GRAPH_CHUNK), &ex);
+  if (s == LBM_OK && n > GRAPH_CHUNK && n % GRAPH_CHUNK >= 2) s = graph_for(c, n % GRAPH_CHUNK, &ex);
+  return s;
 }
 
 extern "C" lbm_status lbm_debug_stream_only(lbm_ctx *c, int64_t n) {
@@ -689,7 +786,8 @@ extern "C" lbm_status lbm_macroscopic(lbm_ctx *c, double *rho, double *u) {
   if (s != LBM_OK) return s;
   if (!dev) {
     HIPCHECK(hipMemcpyAsync(rho, r, n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy rho");
-    HIPCHECK(hipMemcpyAsync(u, v, size_t(c->d) * n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy u");
+    // all three components: the kernel writes u_z = 0 for D2Q9
+    HIPCHECK(hipMemcpyAsync(u, v, 3 * n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy u");
   }
   HIPCHECK(hipStreamSynchronize(c->stream), "macroscopic sync");
   return LBM_OK;
@@ -808,6 +906,7 @@ extern "C" lbm_status lbm_set_launch(lbm_ctx *c, int bx, int by, int swz) {
   c->by = by;
   c->swz = swz ? 1 : 0;
   if (c->vec && !vec_ok(c, bx)) c->vec = false;
+  if (c->stage && !stage_ok(c, bx, by)) c->stage = false;
   if (c->transform == LBM_TRANSFORM_DENSE_MFMA && bx * by > 256) c->transform = LBM_TRANSFORM_CHIMERA;
   return LBM_OK;
 }
@@ -822,6 +921,19 @@ extern "C" lbm_status lbm_set_vectorized(lbm_ctx *c, int enable) {
 }
 
 extern "C" int lbm_get_vectorized(const lbm_ctx *c) { return c && c->vec ? 1 : 0; }
+
+extern "C" lbm_status lbm_set_staged(lbm_ctx *c, int enable) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (enable && !stage_ok(c, c->bx, c->by))
+    return fail(LBM_EUNSUPPORTED, "the LDS variant needs the pull pattern with blocks of 128 x 1 or 256 x 1 "
+                                  "threads, nx a multiple of bx and 16-byte aligned buffers, or the AA pattern "
+                                  "with at most 256 threads and nx a multiple of bx");
+  if (c->stage != (enable != 0)) clear_graphs(c);
+  c->stage = enable != 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_staged(const lbm_ctx *c) { return c && c->stage ? 1 : 0; }
 
 extern "C" lbm_status lbm_set_transform(lbm_ctx *c, int transform) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
@@ -880,17 +992,13 @@ extern "C" lbm_status lbm_buffer(const lbm_ctx *c, int k, void **ptr, size_t *by
 extern "C" lbm_status lbm_time_steps(lbm_ctx *c, int64_t n, double *ms) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   if (!ms) return fail(LBM_EINVAL, "ms is NULL");
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  HIPCHECK(hipEventCreate(&e1), "event");
-  HIPCHECK(hipEventRecord(e0, c->stream), "event record");
+  EventPair ev;
+  HIPCHECK(ev.create(), "event");
+  HIPCHECK(hipEventRecord(ev.e0, c->stream), "event record");
   lbm_status s = lbm_step(c, n);
-  HIPCHECK(hipEventRecord(e1, c->stream), "event record");
-  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  HIPCHECK(hipEventRecord(ev.e1, c->stream), "event record");
   float f = 0.f;
-  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIPCHECK(ev.elapsed(&f), "elapsed");
   *ms = double(f);
   return s;
 }
@@ -902,7 +1010,8 @@ static std::string tune_key(const lbm_ctx *c) {
   std::ostringstream k;
   k << "s" << c->s << "_sp" << c->space << "_eq" << c->eq << "_r" << int(c->reg) << "_st" << c->store << "_pat"
     << c->pattern << "_lay" << c->layout << (c->literal ? "_lit" + std::to_string(c->form) : std::string())
-    << (c->p.zero_centered ? "" : "_abs") << (c->R.cross ? "_cross" : "") << (forced(c) ? "_force" : "") << "_"
+    << (c->p.zero_centered ? "" : "_abs") << (c->R.cross ? "_cross" : "") << (forced(c) ? "_force" : "")
+    << (c->transform == LBM_TRANSFORM_DENSE_MFMA ? "_mfma" : "") << "_"
     << c->nx << "x" << c->ny << "x" << c->nz;
   return k.str();
 }
@@ -961,20 +1070,31 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
   const char *file = std::getenv("LBM_AUTOTUNE_CACHE");
   const std::string key = tune_key(c);
+  // the MFMA ablation kernel takes blocks of at most four waves, stages its own tiles in LDS
+  // and has no vectorised form
+  const bool mfma = c->transform == LBM_TRANSFORM_DENSE_MFMA;
+  const int max_threads = mfma ? 256 : 512;
   int bx, by, swz, vec = 0, lds = 0;
-  if (file && cache_lookup(file, key, &bx, &by, &swz, &vec, &lds)) {
+  // kernel variant of a shape: 0 per-cell registers, 1 vectorised, 2 LDS-staged (pull)
+  auto apply_variant = [&](int v) {
+    lbm_status r = lbm_set_vectorized(c, v == 1 ? 1 : 0);
+    return r != LBM_OK ? r : lbm_set_staged(c, v == 2 ? 1 : 0);
+  };
+  if (file && cache_lookup(file, key, &bx, &by, &swz, &vec, &lds) && bx * by <= max_threads) {
     lbm_status s0 = lbm_set_launch(c, bx, by, swz);
-    if (s0 == LBM_OK) s0 = lbm_set_vectorized(c, vec);
-    return s0 != LBM_OK ? s0 : lbm_set_lds_reserve(c, lds);
+    if (s0 == LBM_OK) s0 = apply_variant(mfma ? 0 : vec);
+    return s0 != LBM_OK ? s0 : lbm_set_lds_reserve(c, mfma ? 0 : lds);
   }
-  // candidate shapes: (bx, by, swizzle, vectorised)
+  // candidate shapes: (bx, by, swizzle, variant)
+  const bool plain = !mfma && !forced(c) && !c->literal && !c->R.cross;  // the default branch of one_step
   std::vector<std::array<int, 4>> cand;
   for (int cbx : {64, 128, 256, 512})
     for (int cby : {1, 2, 4, 8})
       for (int cs : {0, 1})
-        for (int cv : {0, 1}) {
-          if (cbx * cby > 512 || (cbx * cby) % 64 != 0) continue;
-          if (cv && (cbx * cby > 256 || !vec_ok(c, cbx))) continue;
+        for (int cv : {0, 1, 2}) {
+          if (cbx * cby > max_threads || (cbx * cby) % 64 != 0) continue;
+          if (cv == 1 && (mfma || cbx * cby > 256 || !vec_ok(c, cbx))) continue;
+          if (cv == 2 && (!plain || !stage_ok(c, cbx, cby))) continue;
           if (cbx > 64 && cbx / 2 >= c->nx) continue;
           if (cby > 1 && cby / 2 >= c->ny) continue;
           cand.push_back({cbx, cby, cs, cv});
@@ -984,12 +1104,8 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   // the buffer that is restored afterwards and time their even and odd steps alternately, as
   // they run, over an even number of steps
   const bool two = two_buffers(c);
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  if (hipError_t ee = hipEventCreate(&e1); ee != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return hip_fail(ee, "event");
-  }
+  EventPair ev;
+  HIPCHECK(ev.create(), "event");
   void *saved = nullptr;
   if (!two) {
     hipError_t e = hipMalloc(&saved, c->buf_bytes);
@@ -997,54 +1113,58 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
     if (e != hipSuccess) {
       (void)hipGetLastError();
       if (saved) (void)hipFree(saved);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
       return fail(LBM_ENOMEM, "autotuning the in-place pattern needs a temporary copy of the state");
     }
   }
   const int cur0 = c->cur;
   const int64_t t0 = c->t;
   const int bx0 = c->bx, by0 = c->by, swz0 = c->swz, lds0 = c->lds;
-  const bool vec0 = c->vec;
-  c->lds = 0;
+  const bool vec0 = c->vec, stage0 = c->stage;
   const bool g0 = c->graphs;
+  c->lds = 0;
   c->graphs = false;
   const uint64_t lups = uint64_t(c->ncells);
   int reps = int(std::max<uint64_t>(4, std::min<uint64_t>(20, (uint64_t(1) << 27) / std::max<uint64_t>(1, lups) + 2)));
   reps += reps & 1;
+  const bool verbose = std::getenv("LBM_AUTOTUNE_VERBOSE") != nullptr;
+  // time `reps` sweeps (after one warm-up) of the shape cd with LDS reserve c->lds
+  auto time_shape = [&](const std::array<int, 4> &cd, float *ms) -> lbm_status {
+    c->bx = cd[0];
+    c->by = cd[1];
+    c->swz = cd[2];
+    c->vec = cd[3] == 1;
+    c->stage = cd[3] == 2;
+    c->t = t0;
+    lbm_status st = ensure_tiles(c);  // time the launch as lbm_step runs it, with its tile table
+    for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
+      if (r == 1) (void)hipEventRecord(ev.e0, c->stream);
+      c->cur = cur0;
+      if (two) c->t = t0;
+      st = one_step(c);
+    }
+    (void)hipEventRecord(ev.e1, c->stream);
+    const hipError_t e = ev.elapsed(ms);
+    if (st != LBM_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "autotune timing");
+    if (verbose)
+      std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d variant %d lds %d: %.4f ms/step\n", key.c_str(),
+                   cd[0], cd[1], cd[2], cd[3], c->lds, *ms / reps);
+    return LBM_OK;
+  };
   double best = 1e300;
-  int bb[4] = {bx0, by0, swz0, vec0 ? 1 : 0};
+  int bb[4] = {bx0, by0, swz0, vec0 ? 1 : (stage0 ? 2 : 0)};
+  int best_lds = 0;
   // best uncapped shape per block size (64, 128, 256, 512 threads), the starting points of phase 2
   double best_t[4] = {1e300, 1e300, 1e300, 1e300};
   std::array<int, 4> shape_t[4] = {};
   lbm_status st = LBM_OK;
   for (const auto &cd : cand) {
-    c->bx = cd[0];
-    c->by = cd[1];
-    c->swz = cd[2];
-    c->vec = cd[3] != 0;
-    // warm-up, then time reps sweeps; pull: same src -> dst every time
-    c->t = t0;
-    for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
-      if (r == 1) (void)hipEventRecord(e0, c->stream);
-      c->cur = cur0;
-      if (two) c->t = t0;
-      st = one_step(c);
-    }
-    (void)hipEventRecord(e1, c->stream);
-    (void)hipEventSynchronize(e1);
     float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    st = time_shape(cd, &ms);
     if (st != LBM_OK) break;
-    if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
-      std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d vec %d: %.4f ms/step\n", key.c_str(), cd[0],
-                   cd[1], cd[2], cd[3], ms / reps);
     if (ms < best) {
       best = ms;
-      bb[0] = cd[0];
-      bb[1] = cd[1];
-      bb[2] = cd[2];
-      bb[3] = cd[3];
+      for (int k = 0; k < 4; ++k) bb[k] = cd[k];
     }
     const int ti = cd[0] * cd[1] == 64 ? 0 : cd[0] * cd[1] == 128 ? 1 : cd[0] * cd[1] == 256 ? 2 : 3;
     if (ms < best_t[ti]) {
@@ -1055,59 +1175,41 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   // phase 2: occupancy cap (dynamic LDS per block) on the best shape of each block size.  Fewer
   // resident waves than the registers allow can stream faster, so the cap and the block size
   // are chosen together; the ladder holds at most 10, 8, 6, 5, 4, 3 or 2 blocks per CU (160 KiB).
-  int best_lds = 0;
-  for (int ti = 0; ti < 4 && st == LBM_OK; ++ti) {
+  // The MFMA ablation sizes its LDS itself.
+  for (int ti = 0; ti < 4 && st == LBM_OK && !mfma; ++ti) {
     if (best_t[ti] >= 1e300) continue;
-    const std::array<int, 4> &cd = shape_t[ti];
-    c->bx = cd[0];
-    c->by = cd[1];
-    c->swz = cd[2];
-    c->vec = cd[3] != 0;
-    for (int lds : {16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
-      c->lds = lds;
-      c->t = t0;
-      for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
-        if (r == 1) (void)hipEventRecord(e0, c->stream);
-        c->cur = cur0;
-        if (two) c->t = t0;
-        st = one_step(c);
-      }
-      (void)hipEventRecord(e1, c->stream);
-      (void)hipEventSynchronize(e1);
+    for (int l : {16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
+      c->lds = l;
       float ms = 0.f;
-      (void)hipEventElapsedTime(&ms, e0, e1);
+      st = time_shape(shape_t[ti], &ms);
       if (st != LBM_OK) break;
-      if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
-        std::fprintf(stderr, "[lbm autotune] %s bx %d by %d swizzle %d vec %d lds %d: %.4f ms/step\n", key.c_str(),
-                     cd[0], cd[1], cd[2], cd[3], lds, ms / reps);
       if (ms < best) {
         best = ms;
-        bb[0] = cd[0];
-        bb[1] = cd[1];
-        bb[2] = cd[2];
-        bb[3] = cd[3];
-        best_lds = lds;
+        for (int k = 0; k < 4; ++k) bb[k] = shape_t[ti][k];
+        best_lds = l;
       }
     }
   }
+  // restore the state, the step counter and the previous launch on every path
   c->lds = lds0;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   c->cur = cur0;
   c->t = t0;
   c->graphs = g0;
-  if (saved) {
-    (void)hipMemcpyAsync(c->buf[0], saved, c->buf_bytes, hipMemcpyDeviceToDevice, c->stream);
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(saved);
-  }
-  if (st != LBM_OK) return st;
   c->bx = bx0;
   c->by = by0;
   c->swz = swz0;
   c->vec = vec0;
+  c->stage = stage0;
+  if (saved) {
+    const hipError_t e1 = hipMemcpyAsync(c->buf[0], saved, c->buf_bytes, hipMemcpyDeviceToDevice, c->stream);
+    const hipError_t e2 = hipStreamSynchronize(c->stream);
+    (void)hipFree(saved);
+    if (st == LBM_OK && e1 != hipSuccess) return hip_fail(e1, "autotune state restore");
+    if (st == LBM_OK && e2 != hipSuccess) return hip_fail(e2, "autotune state restore");
+  }
+  if (st != LBM_OK) return st;
   lbm_status s2 = lbm_set_launch(c, bb[0], bb[1], bb[2]);
-  if (s2 == LBM_OK) s2 = lbm_set_vectorized(c, bb[3]);
+  if (s2 == LBM_OK) s2 = apply_variant(bb[3]);
   if (s2 == LBM_OK) s2 = lbm_set_lds_reserve(c, best_lds);
   if (s2 == LBM_OK && file) cache_store(file, key, bb[0], bb[1], bb[2], bb[3], best_lds, best / reps);
   return s2;
@@ -1120,22 +1222,18 @@ extern "C" lbm_status lbm_copy_bandwidth(void *dst, const void *src, size_t byte
   const size_t n = bytes / 16;
   if ((n + 255) / 256 > 0x7fffffffu) return fail(LBM_EINVAL, "copy too large for one launch");
   const unsigned blocks = unsigned((n + 255) / 256);
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  HIPCHECK(hipEventCreate(&e1), "event");
+  EventPair ev;
+  HIPCHECK(ev.create(), "event");
   lbm_v4u *d = static_cast<lbm_v4u *>(dst);
   const lbm_v4u *sp = static_cast<const lbm_v4u *>(src);
   void *args[] = {&d, &sp, const_cast<size_t *>(&n)};
   HIPCHECK(hipLaunchKernel(copy_fn(), dim3(blocks), dim3(256), args, 0, s), "copy launch");
-  HIPCHECK(hipEventRecord(e0, s), "event record");
+  HIPCHECK(hipEventRecord(ev.e0, s), "event record");
   for (int r = 0; r < reps; ++r)
     HIPCHECK(hipLaunchKernel(copy_fn(), dim3(blocks), dim3(256), args, 0, s), "copy launch");
-  HIPCHECK(hipEventRecord(e1, s), "event record");
-  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  HIPCHECK(hipEventRecord(ev.e1, s), "event record");
   float f = 0.f;
-  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIPCHECK(ev.elapsed(&f), "elapsed");
   *ms = double(f);
   return LBM_OK;
 }
@@ -1448,6 +1546,10 @@ static lbm_status batch_graph_for(lbm_batch *b, int64_t n, hipGraphExec_t *out) 
   auto key = std::make_pair(n, b->cur);
   auto it = b->gcache.find(key);
   if (it == b->gcache.end()) {
+    if (b->gcache.size() >= GRAPH_CACHE_MAX) {
+      HIPCHECK(hipStreamSynchronize(b->stream), "sync before graph eviction");
+      batch_clear_graphs(b);
+    }
     const int cur0 = b->cur;
     const int64_t t0 = b->t;
     HIPCHECK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
@@ -1484,20 +1586,26 @@ extern "C" lbm_status lbm_batch_step(lbm_batch *b, int64_t n) {
     }
     return LBM_OK;
   }
-  hipGraphExec_t ex = nullptr;
-  lbm_status s = batch_graph_for(b, n, &ex);
-  if (s != LBM_OK) return s;
-  HIPCHECK(hipGraphLaunch(ex, b->stream), "graph launch");
-  b->cur ^= int(n & 1);
-  b->t += n;
-  return LBM_OK;
+  while (n >= 2) {
+    const int64_t m = std::min(n, GRAPH_CHUNK);
+    hipGraphExec_t ex = nullptr;
+    lbm_status s = batch_graph_for(b, m, &ex);
+    if (s != LBM_OK) return s;
+    HIPCHECK(hipGraphLaunch(ex, b->stream), "graph launch");
+    b->cur ^= int(m & 1);
+    b->t += m;
+    n -= m;
+  }
+  return n == 1 ? batch_one_step(b) : LBM_OK;
 }
 
 extern "C" lbm_status lbm_batch_graph_prepare(lbm_batch *b, int64_t n) {
   if (!b) return fail(LBM_EINVAL, "batch is NULL");
   if (n < 2 || !b->graphs) return LBM_OK;
   hipGraphExec_t ex = nullptr;
-  return batch_graph_for(b, n, &ex);
+  lbm_status s = batch_graph_for(b, std::min(n, GRAPH_CHUNK), &ex);
+  if (s == LBM_OK && n > GRAPH_CHUNK && n % GRAPH_CHUNK >= 2) s = batch_graph_for(b, n % GRAPH_CHUNK, &ex);
+  return s;
 }
 
 extern "C" lbm_status lbm_batch_macroscopic(lbm_batch *b, double *rho, double *u) {
@@ -1602,9 +1710,9 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
   const int cur0 = b->cur;
   const int64_t t0 = b->t;
   const int bt0 = b->bt, swz0 = b->swz, lds0 = b->lds;
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  HIPCHECK(hipEventCreate(&e1), "event");
+  EventPair ev;
+  HIPCHECK(ev.create(), "event");
+  hipEvent_t e0 = ev.e0, e1 = ev.e1;
   const int reps = 5;
   double best = 1e300;
   int bb[3] = {bt0, swz0, lds0};
@@ -1641,8 +1749,6 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
     }
     if (st != LBM_OK) break;
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   b->cur = cur0;
   b->t = t0;
   lbm_status s2 = batch_build_tiles(b, st == LBM_OK ? bb[0] : bt0);
@@ -1654,17 +1760,13 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
 
 extern "C" lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms) {
   if (!b || !ms) return fail(LBM_EINVAL, "NULL argument");
-  hipEvent_t e0, e1;
-  HIPCHECK(hipEventCreate(&e0), "event");
-  HIPCHECK(hipEventCreate(&e1), "event");
-  HIPCHECK(hipEventRecord(e0, b->stream), "event record");
+  EventPair ev;
+  HIPCHECK(ev.create(), "event");
+  HIPCHECK(hipEventRecord(ev.e0, b->stream), "event record");
   lbm_status s = lbm_batch_step(b, n);
-  HIPCHECK(hipEventRecord(e1, b->stream), "event record");
-  HIPCHECK(hipEventSynchronize(e1), "event sync");
+  HIPCHECK(hipEventRecord(ev.e1, b->stream), "event record");
   float f = 0.f;
-  HIPCHECK(hipEventElapsedTime(&f, e0, e1), "elapsed");
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  HIPCHECK(ev.elapsed(&f), "elapsed");
   *ms = double(f);
   return s;
 }

@@ -87,6 +87,8 @@ SIGNATURES = {
     "lbm_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     "lbm_set_vectorized": (c_int, [c_void_p, c_int]),
     "lbm_get_vectorized": (c_int, [c_void_p]),
+    "lbm_set_staged": (c_int, [c_void_p, c_int]),
+    "lbm_get_staged": (c_int, [c_void_p]),
     "lbm_set_transform": (c_int, [c_void_p, c_int]),
     "lbm_get_transform": (c_int, [c_void_p]),
     "lbm_get_layout": (c_int, [c_void_p]),
@@ -307,6 +309,12 @@ class Lattice:
 
     def lbm_get_vectorized(self):
         return bool(self.lib.lbm_get_vectorized(self.ctx))
+
+    def lbm_set_staged(self, enable):
+        check(self.lib.lbm_set_staged(self.ctx, 1 if enable else 0))
+
+    def lbm_get_staged(self):
+        return bool(self.lib.lbm_get_staged(self.ctx))
 
     def lbm_set_transform(self, transform):
         check(self.lib.lbm_set_transform(self.ctx, {"chimera": 0, "dense_mfma": 1}[transform]))
