@@ -513,7 +513,7 @@ def test_absolute_storage_fp64_matches_oracle(space, streaming):
 def test_tgv128_fp32_and_fp64_against_the_oracle_reference():
     """The 128^3 copy of the D3Q27 cumulant Taylor-Green workload (u0 = 0.05, the 512^3 rates),
     200 steps, against the FP64 oracle's velocity and density at 4096 sampled cells
-    (tests/golden/tgv128_cumulant_oracle.npz, written by make_tgv128_reference.py from the
+    (tests/golden/tgv128_cumulant_oracle.npz, written by make_oracle_references.py from the
     oracle alone): FP32 relative L2 velocity error <= 1e-5, FP64 <= 1e-10."""
     import os
     ref = np.load(os.path.join(os.path.dirname(__file__), "golden", "tgv128_cumulant_oracle.npz"))
