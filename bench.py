@@ -235,21 +235,30 @@ def _oracle_collide_slab(args):
     return O.collide(_oracle_method(spec), slab)
 
 
+def _oracle_init_slab(args):
+    import oracle as O
+    spec, rho, u = args
+    return O.init_equilibrium(_oracle_method(spec), rho, u)
+
+
 def _oracle_rate(spec, fields, steps, procs):
     """Oracle MLUPS of `steps` steps from the equilibrium of `fields`: collide on `procs` slabs in
     a process pool (procs > 1) or in this process, then stream; init is not timed."""
     import oracle as O
     m = _oracle_method(spec)
-    df = O.init_equilibrium(m, *fields)
-    cells = fields[0].size
-    axis = 1 if df.shape[1] > 1 else 2
+    rho, u = fields
+    cells = rho.size
     if procs == 1:
+        df = O.init_equilibrium(m, rho, u)
         t0 = time.perf_counter()
         O.step(m, df, steps)
         return cells * steps / (time.perf_counter() - t0) / 1e6
     from multiprocessing import get_context
     with get_context("fork").Pool(procs) as pool:
-        pool.map(_oracle_collide_slab, [(spec, s) for s in np.array_split(df[:, :procs], procs, axis=axis)])
+        axis = 0 if rho.shape[0] > 1 else 1  # z-slabs (y-slabs of a 2-D box)
+        parts = zip(np.array_split(rho, procs, axis=axis), np.array_split(u, procs, axis=axis + 1))
+        df = np.concatenate(pool.map(_oracle_init_slab, [(spec, r, v) for r, v in parts]), axis=axis + 1)
+        axis = 1 if df.shape[1] > 1 else 2
         t0 = time.perf_counter()
         for _ in range(steps):
             slabs = np.array_split(df, procs, axis=axis)

@@ -263,7 +263,8 @@ lbm_status lbm_get_populations(lbm_ctx *ctx, double *df);
 lbm_status lbm_set_populations(lbm_ctx *ctx, const double *df);
 
 /* FP64 reductions over df(t): out = {sum drho, sum jx, sum jy, sum jz,
- * sum rho |u|^2 / 2 with u = j / rho, number of non-finite populations}.  Deterministic (fixed-order tree).
+ * sum rho |u|^2 / 2 with u = j / rho, number of non-finite populations}.  Deterministic (wave
+ * butterflies and block sums in a fixed order).
  * Returns LBM_ENONFINITE when out[5] > 0 (out is still filled).  Synchronous. */
 lbm_status lbm_diagnostics(lbm_ctx *ctx, double out[6]);
 

@@ -721,10 +721,37 @@ __global__ void __launch_bounds__(256) macro_kernel(FieldArgs a) {
 
 // grid-stride over cells in a fixed order per thread, block tree in LDS -> deterministic
 constexpr int DIAG_THREADS = 256;
+
+// Sum of v over the 64 lanes of a wave by a butterfly of lane exchanges (the lanes pair up
+// at distances 32, 16, ..., 1); every lane ends with the total.  The order of the additions
+// is fixed, so the result is reproducible bit for bit.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// Six block-wide sums of DIAG_THREADS threads: wave sums first, then the DIAG_THREADS / 64
+// wave totals in wave order; red[k][0] holds sum k afterwards (fixed order, deterministic).
+__device__ __forceinline__ void block_sum6(const double acc[6], double (*red)[DIAG_THREADS / 64]) {
+  const int lane = int(threadIdx.x) & 63, wave = int(threadIdx.x) >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const double w = wave_sum(acc[k]);
+    if (lane == 0) red[k][wave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double t = 0.0;
+    for (int w = 0; w < DIAG_THREADS / 64; ++w) t += red[threadIdx.x][w];
+    red[threadIdx.x][0] = t;
+  }
+  __syncthreads();
+}
 template <int S, int GM, class ST>
 __global__ void __launch_bounds__(DIAG_THREADS) diag_kernel(FieldArgs a) {
   using L = Lat<S>;
-  __shared__ double red[6][DIAG_THREADS];
+  __shared__ double red[6][DIAG_THREADS / 64];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   const uint32_t nrow = uint32_t(a.ny) * uint32_t(a.nz);
   const uint64_t total = uint64_t(a.ncells);
@@ -755,16 +782,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) diag_kernel(FieldArgs a) {
     acc[4] += 0.5 * (j[0] * j[0] + j[1] * j[1] + j[2] * j[2]) / (1.0 + drho);
     acc[5] += bad;
   }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s) {
-#pragma unroll
-      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
+  block_sum6(acc, red);
   if (threadIdx.x < 6) a.partials[size_t(blockIdx.x) * 6 + threadIdx.x] = red[threadIdx.x][0];
 }
 

@@ -70,17 +70,11 @@ const void *macro_fn(int s, int store, int gm) { LBM_TABLE_CALL(macro, gm) }
 const void *diag_fn(int s, int store, int gm) { LBM_TABLE_CALL(diag, gm) }
 
 __global__ void __launch_bounds__(DIAG_THREADS) diag_final_kernel(const double *partials, int nblocks, double *out) {
-  __shared__ double red[6][DIAG_THREADS];
+  __shared__ double red[6][DIAG_THREADS / 64];
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblocks; b += DIAG_THREADS)
     for (int k = 0; k < 6; ++k) acc[k] += partials[size_t(b) * 6 + k];
-  for (int k = 0; k < 6; ++k) red[k][threadIdx.x] = acc[k];
-  __syncthreads();
-  for (int s = DIAG_THREADS / 2; s > 0; s >>= 1) {
-    if (int(threadIdx.x) < s)
-      for (int k = 0; k < 6; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
-    __syncthreads();
-  }
+  block_sum6(acc, red);
   if (threadIdx.x < 6) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
