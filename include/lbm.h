@@ -268,6 +268,22 @@ lbm_status lbm_set_populations(lbm_ctx *ctx, const double *df);
  * Returns LBM_ENONFINITE when out[5] > 0 (out is still filled).  Synchronous. */
 lbm_status lbm_diagnostics(lbm_ctx *ctx, double out[6]);
 
+/* Allocation-free variant of lbm_diagnostics, for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * reductions and the same results as lbm_diagnostics, but the per-block partial sums go to a
+ * static device array of LBM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends; the call allocates nothing.
+ * out: 6 doubles.  Device memory: the two reduction kernels are queued on the context stream
+ * and the call returns without synchronising (out[5] carries the non-finite count; no
+ * LBM_ENONFINITE).  Host memory: the call synchronises and returns LBM_ENONFINITE like
+ * lbm_diagnostics.
+ * The array is shared by every call on one GPU and keeps the last call's contents: calls that
+ * overlap on one GPU (other streams, other threads, other contexts) race and must be ordered
+ * by the caller.  The context's device must be current (LBM_EINVAL otherwise).
+ * LBM_EUNSUPPORTED if the reduction would need more than LBM_NOALLOC_SCRATCH_BYTES (it needs
+ * 48 bytes per reduction block, at most 2048 blocks, plus 48). */
+#define LBM_NOALLOC_SCRATCH_BYTES (128 * 1024)
+lbm_status lbm_diagnostics_noalloc(lbm_ctx *ctx, double *out);
 /* Wait for all work queued on the context stream. */
 lbm_status lbm_synchronize(lbm_ctx *ctx);
 

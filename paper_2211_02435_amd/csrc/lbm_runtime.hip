@@ -10,6 +10,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <mutex>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -169,6 +170,7 @@ struct lbm_ctx {
   size_t staging_doubles = 0;
   double *partials = nullptr;
   int diag_blocks = 0;
+  int device = 0;     // the device that was current at lbm_create
   // block -> tile tables of the sweep for the current launch shape (index 1: vectorised);
   // tile_key is the (bx, by, swz) they were built for
   uint2 *tiles[2] = {nullptr, nullptr};
@@ -575,6 +577,10 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
   c->by = std::max(1, 256 / bx);
   c->swz = 0;
   c->diag_blocks = int(std::min<uint64_t>(2048, (uint64_t(c->ncells) + DIAG_THREADS - 1) / DIAG_THREADS));
+  if (hipError_t ed = hipGetDevice(&c->device); ed != hipSuccess) {
+    lbm_destroy(c);
+    return hip_fail(ed, "current device");
+  }
   hipError_t e = hipMalloc(&c->partials, (size_t(c->diag_blocks) * 6 + 8) * sizeof(double));
   if (e != hipSuccess) {
     lbm_destroy(c);
@@ -850,6 +856,68 @@ extern "C" lbm_status lbm_diagnostics(lbm_ctx *c, double out[6]) {
   int nb = c->diag_blocks;
   void *args2[] = {&c->partials, &nb, &dout};
   HIPCHECK(hipLaunchKernel(diag_final_fn(), dim3(1), dim3(DIAG_THREADS), args2, 0, c->stream), "diag final launch");
+  HIPCHECK(hipMemcpyAsync(out, dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "diag copy");
+  HIPCHECK(hipStreamSynchronize(c->stream), "diag sync");
+  if (out[5] > 0.0) return fail(LBM_ENONFINITE, "non-finite populations found");
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// allocation-free diagnostics: the partial sums live in a static device array (one copy per
+// GPU, kept until the process ends) instead of the context's buffer
+// ---------------------------------------------------------------------------------------
+namespace lbm {
+static constexpr size_t NOALLOC_SCRATCH_DOUBLES = size_t(LBM_NOALLOC_SCRATCH_BYTES) / sizeof(double);
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+static constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static double *g_scratch_dev[MAX_DEVICES] = {};
+
+// Device address of this GPU's scratch array; looked up once per device, with that device
+// current (the host-side name of the array is not a device address).
+static lbm_status scratch_ptr(int device, double **out) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(LBM_EDEVICE, "device index out of range for the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "scratch symbol address");
+    g_scratch_dev[device] = static_cast<double *>(p);
+  }
+  *out = g_scratch_dev[device];
+  return LBM_OK;
+}
+}  // namespace lbm
+
+extern "C" lbm_status lbm_diagnostics_noalloc(lbm_ctx *c, double *out) {
+  if (check_ctx(c) != LBM_OK) return LBM_EINVAL;
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  int dev = -1;
+  HIPCHECK(hipGetDevice(&dev), "current device");
+  if (dev != c->device) return fail(LBM_EINVAL, "the context's device must be current");
+  const int nb = c->diag_blocks;
+  const size_t need = size_t(nb) * 6 + 6;  // partials, then the six sums for a host destination
+  if (need > NOALLOC_SCRATCH_DOUBLES)
+    return fail(LBM_EUNSUPPORTED, "the reduction needs " + std::to_string(need * sizeof(double)) +
+                                      " bytes of scratch, more than the " +
+                                      std::to_string(LBM_NOALLOC_SCRATCH_BYTES) + " the library holds");
+  double *sp = nullptr;
+  lbm_status st = scratch_ptr(dev, &sp);
+  if (st != LBM_OK) return st;
+  const void *fn = diag_fn(c->s, c->store, state_gather_mode(c));
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no diagnostics kernel");
+  // every block writes all six of its partials and the final kernel reads exactly nb blocks,
+  // so nothing left in the array by an earlier call is read
+  FieldArgs a = field_args(c, state_buffer(c), FBX, FBY);
+  a.partials = sp;
+  void *args[] = {&a};
+  HIPCHECK(hipLaunchKernel(fn, dim3(nb), dim3(DIAG_THREADS), args, 0, c->stream), "diag launch");
+  const bool dev_out = is_device_ptr(out);
+  double *dout = dev_out ? out : sp + size_t(nb) * 6;
+  int nbv = nb;
+  void *args2[] = {&sp, &nbv, &dout};
+  HIPCHECK(hipLaunchKernel(diag_final_fn(), dim3(1), dim3(DIAG_THREADS), args2, 0, c->stream), "diag final launch");
+  if (dev_out) return LBM_OK;
   HIPCHECK(hipMemcpyAsync(out, dout, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream), "diag copy");
   HIPCHECK(hipStreamSynchronize(c->stream), "diag sync");
   if (out[5] > 0.0) return fail(LBM_ENONFINITE, "non-finite populations found");

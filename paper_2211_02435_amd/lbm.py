@@ -80,6 +80,7 @@ SIGNATURES = {
     "lbm_set_populations": (c_int, [c_void_p, c_void_p]),
     "lbm_set_force_field": (c_int, [c_void_p, c_void_p]),
     "lbm_diagnostics": (c_int, [c_void_p, POINTER(c_double)]),
+    "lbm_diagnostics_noalloc": (c_int, [c_void_p, c_void_p]),
     "lbm_synchronize": (c_int, [c_void_p]),
     "lbm_time": (c_int64, [c_void_p]),
     "lbm_set_time": (c_int, [c_void_p, c_int64]),
@@ -286,6 +287,18 @@ class Lattice:
         if not (allow_nonfinite and s == LBM_ENONFINITE):
             check(s)
         return np.array(out[:])
+
+    def lbm_diagnostics_noalloc(self, out=None, allow_nonfinite=False):
+        """Allocation-free diagnostics: into `out` (a device tensor of 6 doubles; asynchronous)
+        or, without `out`, into a host array (synchronous)."""
+        if out is not None:
+            check(self.lib.lbm_diagnostics_noalloc(self.ctx, _dptr(out)))
+            return out
+        host = np.empty(6)
+        s = self.lib.lbm_diagnostics_noalloc(self.ctx, _dptr(host))
+        if not (allow_nonfinite and s == LBM_ENONFINITE):
+            check(s)
+        return host
 
     def lbm_synchronize(self):
         check(self.lib.lbm_synchronize(self.ctx))
