@@ -28,14 +28,15 @@ sys.path.insert(0, ROOT)
 import lbm_workloads as W  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_{workload}_{storage}.json")
 SBYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def measured_traffic(workload, layout):
+def measured_traffic(workload, layout, storage="f32"):
     """HBM bytes per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel sources and the same storage layout; else None."""
-    path = TRAFFIC_FILE.format(workload=workload)
+    current kernel sources (device code, runtime, build flags) and the same storage layout;
+    else None."""
+    path = TRAFFIC_FILE.format(workload=workload, storage=storage)
     if not os.path.exists(path):
         return None
     from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
@@ -424,6 +425,10 @@ def main():
         print("[bench] accuracy vs oracle: %s" % json.dumps(accuracy), file=sys.stderr, flush=True)
 
     r = runs[main_st]
+    plain = (n == cfg["dims"][0] and args.streaming == "pull" and args.transform == "chimera"
+             and args.rates == "regularized" and not args.launch)
+    if "f64" in runs and main_st != "f64":
+        runs["f64"]["traffic"] = measured_traffic(name, runs["f64"].get("layout"), "f64") if plain else None
     fields_desc = ("shallow water g 0.1, 16 Gaussian bumps" if name == "swe_d2q9_4096"
                    else "Taylor-Green u0 %.2f" % cfg["u0"])
     workload = "%s %s %s periodic, %s, omega_s %.6f, %s, %s" % (
@@ -449,10 +454,7 @@ def main():
                    "launch_bx_by_swizzle_variant_lds": r["launch_bx_by_swizzle_variant_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
-                     "traffic": measured_traffic(name, r.get("layout")) if (n == cfg["dims"][0] and main_st == "f32"
-                                                           and args.streaming == "pull"
-                                                           and args.transform == "chimera"
-                                                           and args.rates == "regularized") else None,
+                     "traffic": measured_traffic(name, r.get("layout"), main_st) if plain else None,
                      "kernel": "sweep_kernel<%s, %s, %s, %s, %s>" % (cfg["stencil"], cfg["space"], args.rates,
                                                                      main_st, args.streaming),
                      "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},

@@ -7,7 +7,17 @@
       --kernel <substring> --copy-bytes <bytes> --workload <name> [--layout planes|rows] [--out <json>]
       HBM bytes per launch of the kernel from FETCH_SIZE and WRITE_SIZE (KiB per dispatch),
       each scaled by what the same counter reads for the plain copy kernel of known size,
-      together with the hash of the kernel sources the counters were taken on.
+      together with the hash of the sources and build flags the counters were taken on.
+
+  python -m paper_2211_02435_amd.rocprof_summary counters <db> [<db> ...] [--match sweep]
+      median value per dispatch of every PMC counter in the databases, per kernel
+
+  python -m paper_2211_02435_amd.rocprof_summary memory <db> [<db> ...] --copy-bytes <bytes>
+      the memory-interface view of every sweep and copy kernel from the passes FETCH_SIZE;
+      WRITE_SIZE; TCC_EA0_{RD,WR}REQ{,_LEVEL}_sum with GRBM_GUI_ACTIVE;
+      TCC_EA0_WRREQ_64B_sum, TCC_EA0_WRREQ_STALL_sum, TCC_EA0_{RD,WR}REQ_DRAM_CREDIT_STALL_sum
+      with GRBM_GUI_ACTIVE: bytes moved, bytes per request, average request latency and
+      requests in flight (Little's law: level / requests, level / cycles), stall fractions
 """
 import argparse
 import hashlib
@@ -17,12 +27,22 @@ import sqlite3
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL_SOURCES = ["paper_2211_02435_amd/csrc/lbm_device.hpp", "paper_2211_02435_amd/csrc/lbm_kernels.hpp"]
+CSRC = "paper_2211_02435_amd/csrc"
+
+
+def kernel_sources():
+    """Every file that decides what the measured kernels do and how they are launched: the
+    device code, the runtime (launch shapes, tile tables, LDS reserve), the instantiation
+    units and the build script with its compiler flags."""
+    files = sorted(os.path.join(CSRC, f) for f in os.listdir(os.path.join(ROOT, CSRC))
+                   if f.endswith((".hpp", ".hip", ".inc", ".cpp")))
+    return files + ["paper_2211_02435_amd/build.py", "include/lbm.h"]
 
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in kernel_sources():
+        h.update(rel.encode())
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -79,6 +99,63 @@ def counter_per_dispatch(db, counter):
     return out
 
 
+def all_counters(db):
+    """{counter name: {kernel name: [value per dispatch]}} for every PMC counter in db."""
+    con = sqlite3.connect(db)
+    try:
+        names = [r[0] for r in con.execute("select distinct name from pmc_info")]
+    except sqlite3.OperationalError:
+        names = [r[0] for r in con.execute("select distinct counter_name from counters_collection")]
+    con.close()
+    return {n: counter_per_dispatch(db, n) for n in names}
+
+
+def counters_table(dbs, match=None):
+    """Median per dispatch of every counter of every database, per kernel."""
+    rows = {}
+    for db in dbs:
+        for name, per_kernel in all_counters(db).items():
+            for k, vals in per_kernel.items():
+                if match and match not in k:
+                    continue
+                vals = sorted(vals)
+                rows.setdefault(k, {})[name] = vals[len(vals) // 2]
+    return rows
+
+
+XCDS = 8           # GRBM_GUI_ACTIVE is summed over the XCDs
+TCC_CHANNELS = 128  # the _sum counters are summed over 16 L2 channels on each of the 8 XCDs
+
+
+def memory_view(dbs, copy_bytes, clock_ghz=2.1):
+    """Derived memory-interface figures per kernel (see the module docstring)."""
+    t = counters_table(dbs)
+    copy = [v for k, v in t.items() if "copy_kernel" in k]
+    if not copy:
+        raise SystemExit("no copy_kernel dispatch to scale FETCH_SIZE / WRITE_SIZE")
+    sf = copy_bytes / (copy[0]["FETCH_SIZE"] * 1024.0)
+    sw = copy_bytes / (copy[0]["WRITE_SIZE"] * 1024.0)
+    out = []
+    for k, v in t.items():
+        if not ("sweep" in k or "copy_kernel" in k):
+            continue
+        cyc = v["GRBM_GUI_ACTIVE"] / XCDS
+        rd, wr = v["TCC_EA0_RDREQ_sum"], v["TCC_EA0_WRREQ_sum"]
+        fb, wb = v["FETCH_SIZE"] * 1024.0 * sf, v["WRITE_SIZE"] * 1024.0 * sw
+        out.append({"kernel": k, "fetch_GB": fb / 1e9, "write_GB": wb / 1e9,
+                    "bytes_per_read_req": fb / rd, "bytes_per_write_req": wb / wr,
+                    "write_64B_fraction": v["TCC_EA0_WRREQ_64B_sum"] / wr,
+                    "read_latency_cycles": v["TCC_EA0_RDREQ_LEVEL_sum"] / rd,
+                    "write_latency_cycles": v["TCC_EA0_WRREQ_LEVEL_sum"] / wr,
+                    "reads_in_flight": v["TCC_EA0_RDREQ_LEVEL_sum"] / cyc,
+                    "writes_in_flight": v["TCC_EA0_WRREQ_LEVEL_sum"] / cyc,
+                    "write_stall_fraction": v["TCC_EA0_WRREQ_STALL_sum"] / cyc / TCC_CHANNELS,
+                    "read_credit_stall_fraction": v["TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum"] / cyc / TCC_CHANNELS,
+                    "write_credit_stall_fraction": v["TCC_EA0_WRREQ_DRAM_CREDIT_STALL_sum"] / cyc / TCC_CHANNELS,
+                    "ms": cyc / (clock_ghz * 1e6)})
+    return out
+
+
 def traffic(fetch_db, write_db, kernel, copy_bytes, workload, layout=None):
     f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
     w = counter_per_dispatch(write_db, "WRITE_SIZE")
@@ -116,6 +193,12 @@ def main(argv=None):
     t.add_argument("--workload", required=True)
     t.add_argument("--layout", default=None, help="storage layout of the profiled run (planes / rows)")
     t.add_argument("--out", default=None)
+    c = sub.add_parser("counters")
+    c.add_argument("dbs", nargs="+")
+    c.add_argument("--match", default=None)
+    m = sub.add_parser("memory")
+    m.add_argument("dbs", nargs="+")
+    m.add_argument("--copy-bytes", type=float, required=True)
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         rows = stats(a.db, a.match, a.last)
@@ -123,6 +206,20 @@ def main(argv=None):
         for r in rows:
             print("%-110s %6d %12.1f %10.1f %10.1f %10.1f" % (r["kernel"][:110], r["calls"], r["total_us"],
                                                                r["avg_us"], r["min_us"], r["max_us"]))
+    elif a.cmd == "memory":
+        print("%-72s %7s %7s %5s %5s %5s %7s %6s %7s %7s %6s %6s %7s" % (
+            "kernel", "rd GB", "wr GB", "B/rd", "B/wr", "wr64", "rd lat", "wr lat", "rd fly", "wr fly",
+            "wstall", "rcred", "busy ms"))
+        for r in memory_view(a.dbs, a.copy_bytes):
+            print("%-72s %7.2f %7.2f %5.0f %5.0f %5.2f %7.0f %6.0f %7.0f %7.0f %6.3f %6.3f %7.3f" % (
+                r["kernel"][:72], r["fetch_GB"], r["write_GB"], r["bytes_per_read_req"], r["bytes_per_write_req"],
+                r["write_64B_fraction"], r["read_latency_cycles"], r["write_latency_cycles"], r["reads_in_flight"],
+                r["writes_in_flight"], r["write_stall_fraction"], r["read_credit_stall_fraction"], r["ms"]))
+    elif a.cmd == "counters":
+        for k, vals in counters_table(a.dbs, a.match).items():
+            print(k[:150])
+            for n in sorted(vals):
+                print("    %-40s %20.1f" % (n, vals[n]))
     else:
         res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload, a.layout)
         txt = json.dumps(res, indent=1)

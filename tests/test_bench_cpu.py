@@ -20,10 +20,21 @@ def test_traffic_record_matches_layout_and_sources(tmp_path, monkeypatch):
     sys.path.insert(0, ROOT)
     import bench
     from paper_2211_02435_amd.rocprof_summary import kernel_source_hash
-    rec = os.path.join(ROOT, "profiles", "traffic_d3q27_cumulant_512.json")
-    t = json.load(open(rec))
-    if t["kernel_source_sha"] == kernel_source_hash():
-        assert bench.measured_traffic("d3q27_cumulant_512", t["layout"]) == t["bytes_per_launch"]
-    other = "planes" if t["layout"] == "rows" else "rows"
-    assert bench.measured_traffic("d3q27_cumulant_512", other) is None
-    assert bench.measured_traffic("no_such_workload", t["layout"]) is None
+    for storage in ("f32", "f64"):
+        rec = os.path.join(ROOT, "profiles", "traffic_d3q27_cumulant_512_%s.json" % storage)
+        t = json.load(open(rec))
+        if t["kernel_source_sha"] == kernel_source_hash():
+            assert bench.measured_traffic("d3q27_cumulant_512", t["layout"], storage) == t["bytes_per_launch"]
+        other = "planes" if t["layout"] == "rows" else "rows"
+        assert bench.measured_traffic("d3q27_cumulant_512", other, storage) is None
+        assert bench.measured_traffic("no_such_workload", t["layout"], storage) is None
+    assert bench.measured_traffic("d3q27_cumulant_512", "rows", "f16") is None
+
+
+def test_traffic_hash_covers_runtime_and_build_flags():
+    sys.path.insert(0, ROOT)
+    from paper_2211_02435_amd import rocprof_summary as R
+    files = R.kernel_sources()
+    for needed in ("paper_2211_02435_amd/csrc/lbm_runtime.hip", "paper_2211_02435_amd/csrc/lbm_instantiate.inc",
+                   "paper_2211_02435_amd/csrc/k_d3q27_f32.hip", "paper_2211_02435_amd/build.py"):
+        assert needed in files
