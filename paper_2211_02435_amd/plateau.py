@@ -21,9 +21,8 @@ This module runs that experiment on the GPU through the library:
     blocks, so the runs take the graded basis, which the literal forms also accept;
   * the vortex does not vary along z and every cell is updated by the same arithmetic, so all
     z-planes stay bit-identical and an L x L x nz box gives the E/E0 of the L^3 box for any nz;
-  * with FP16 storage (FP32 arithmetic) the table has one more column: absolute storage
-    collided by the deviation arithmetic, which separates the storage format from the
-    arithmetic.
+  * one more column, absolute storage collided by the deviation arithmetic, separates the
+    storage format from the arithmetic's operation order.
 
   python -m paper_2211_02435_amd.plateau [--n 256] [--nz 1] [--steps 200000]
       [--storage f64|f32|f16] [--every 20000] [--json out.json]
@@ -48,13 +47,15 @@ COLUMNS = [
 ]
 
 
-# FP16 storage: also absolute storage under the deviation arithmetic (the storage format alone)
+# Absolute storage collided by the deviation arithmetic: the storage format alone, with the
+# collision's operation order taken from the deviation form (every sweep subtracts the
+# weights after loading and adds them back before storing)
 ABS_DEVIATION = ("absolute storage, deviation arithmetic",
                  dict(zero_centered=False, eq_form="default", arithmetic="deviation"))
 
 
 def columns(storage):
-    return COLUMNS + [ABS_DEVIATION] if storage == "f16" else COLUMNS
+    return COLUMNS + [ABS_DEVIATION]
 
 
 def admissible(space, column):
