@@ -146,7 +146,8 @@ def measure_batch(lbm, steps, warmup):
     res = {"boxes": len(boxes), "cells": cells, "steps": steps, "graph_steps": steps,
            "mlups": cells * steps / wall / 1e6, "ms_per_step": wall * 1e3 / steps,
            "avg_launch_ms": ms / steps, "achieved_GBps": gbs, "frac": gbs / HBM_PEAK_GBS,
-           "storage": "f32", "space": "central", "launch_threads_swizzle_lds": list(launch)}
+           "storage": "f32", "space": "central",
+           "launch_threads_swizzle_lds_persistent": list(launch) + [int(bat.lbm_batch_get_persistent())]}
     res["vs_oracle"] = batch_accuracy(lbm, bat, boxes, dims, rho, u)
     return res
 

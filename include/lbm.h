@@ -404,8 +404,14 @@ lbm_status lbm_batch_time_steps(lbm_batch *b, int64_t n, double *ms);
  * values out of range. */
 lbm_status lbm_batch_set_launch(lbm_batch *b, int threads, int swizzle, int lds_bytes);
 lbm_status lbm_batch_get_launch(const lbm_batch *b, int *threads, int *swizzle, int *lds_bytes);
-/* Times one sweep for every tile size in {64, 128, 256, 512}, both tile orders and the LDS
- * reserves {0, 16, 20, 26, 32, 40, 52, 64} KiB, and keeps the fastest.  The state and the step counter
+/* Grid form of the ensemble sweep: 0 (default) one block per tile; 1 persistent, a grid of as
+ * many blocks as the device holds at once for the current tile size and LDS reserve (a multiple
+ * of 8), each block striding over the tile list (in XCD order with the swizzle).  Results do
+ * not depend on it.  The grid follows later lbm_batch_set_launch calls. */
+lbm_status lbm_batch_set_persistent(lbm_batch *b, int enable);
+int lbm_batch_get_persistent(const lbm_batch *b);
+/* Times one sweep for every tile size in {64, 128, 256, 512}, both tile orders, the LDS
+ * reserves {0, 16, 20, 26, 32, 40, 52, 64} KiB and both grid forms, and keeps the fastest.  The state and the step counter
  * are left unchanged (each timed sweep writes only the other buffer).  Synchronous. */
 lbm_status lbm_batch_autotune(lbm_batch *b);
 

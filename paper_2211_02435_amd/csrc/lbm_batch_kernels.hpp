@@ -6,7 +6,9 @@
 // memory order (x fastest; the tile size is a launch parameter, chosen by the autotuner), so
 // every block reads and writes contiguous rows whatever the box edge.  Blocks
 // take tiles in XCD order (each XCD a contiguous range), so the cache lines that neighbouring
-// tiles share are fetched into one L2.
+// tiles share are fetched into one L2.  Two grid forms: one block per tile, or a persistent
+// grid of as many blocks as fit on the chip at once, each striding over the tile list (the
+// stride is a multiple of 8, so a block keeps to its XCD's range in XCD order).
 #pragma once
 
 #include "lbm_kernels.hpp"
@@ -29,15 +31,15 @@ struct BatchArgs {
   const uint32_t *tile_box;  // box of every tile
   const Relax<CT> *relax;    // per-box relaxation blocks
   int swizzle;               // nonzero: consecutive tiles on one XCD (shared boundary lines in one L2)
+  uint32_t ntiles;           // tiles in the list (the persistent form's loop bound)
 };
 
 constexpr int BATCH_THREADS = 256;      // default tile size (cells = threads per block)
 constexpr int BATCH_MAX_THREADS = 512;
 
 template <int S, int SP, int EQ, bool REG, class ST, class CT>
-__global__ void __launch_bounds__(BATCH_MAX_THREADS) batch_sweep_kernel(BatchArgs<ST, CT> a) {
+__device__ __forceinline__ void batch_tile(const BatchArgs<ST, CT> &a, uint32_t tile) {
   using L = Lat<S>;
-  const uint32_t tile = a.swizzle ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t b = a.tile_box[tile];
   const BoxInfo B = a.boxes[b];
   const uint32_t c = (tile - B.tile0) * blockDim.x + threadIdx.x;
@@ -64,11 +66,22 @@ __global__ void __launch_bounds__(BATCH_MAX_THREADS) batch_sweep_kernel(BatchArg
   });
 }
 
+template <int S, int SP, int EQ, bool REG, class ST, class CT, bool PERSIST = false>
+__global__ void __launch_bounds__(BATCH_MAX_THREADS) batch_sweep_kernel(BatchArgs<ST, CT> a) {
+  if constexpr (!PERSIST) {
+    batch_tile<S, SP, EQ, REG>(a, a.swizzle ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x);
+  } else {
+    // the loop index k runs on XCD k % 8 (gridDim.x % 8 == 0), the XCD that xcd_tile assigns it to
+    for (uint32_t k = blockIdx.x; k < a.ntiles; k += gridDim.x)
+      batch_tile<S, SP, EQ, REG>(a, a.swizzle ? xcd_tile(k, a.ntiles) : k);
+  }
+}
+
 template <int S, int STORE>
 struct BTable {
-  static const void *sweep(int sp, int reg);
+  static const void *sweep(int sp, int reg, bool persistent);
 };
 
-const void *batch_sweep_fn(int s, int store, int sp, int reg);
+const void *batch_sweep_fn(int s, int store, int sp, int reg, bool persistent);
 
 }  // namespace lbm

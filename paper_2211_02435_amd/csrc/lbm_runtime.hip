@@ -1306,14 +1306,14 @@ extern "C" lbm_status lbm_copy_bandwidth(void *dst, const void *src, size_t byte
 #include "lbm_batch_kernels.hpp"
 
 namespace lbm {
-const void *batch_sweep_fn(int s, int store, int sp, int reg) {
+const void *batch_sweep_fn(int s, int store, int sp, int reg, bool persistent) {
   switch (s * 3 + store) {
-    case 3: return BTable<D3Q19, F64>::sweep(sp, reg);
-    case 4: return BTable<D3Q19, F32>::sweep(sp, reg);
-    case 5: return BTable<D3Q19, F16>::sweep(sp, reg);
-    case 6: return BTable<D3Q27, F64>::sweep(sp, reg);
-    case 7: return BTable<D3Q27, F32>::sweep(sp, reg);
-    case 8: return BTable<D3Q27, F16>::sweep(sp, reg);
+    case 3: return BTable<D3Q19, F64>::sweep(sp, reg, persistent);
+    case 4: return BTable<D3Q19, F32>::sweep(sp, reg, persistent);
+    case 5: return BTable<D3Q19, F16>::sweep(sp, reg, persistent);
+    case 6: return BTable<D3Q27, F64>::sweep(sp, reg, persistent);
+    case 7: return BTable<D3Q27, F32>::sweep(sp, reg, persistent);
+    case 8: return BTable<D3Q27, F16>::sweep(sp, reg, persistent);
   }
   return nullptr;
 }
@@ -1343,12 +1343,28 @@ struct lbm_batch {
   int swz = 1;  // XCD-ordered tiles (LBM_BATCH_SWIZZLE=0 switches it off)
   int bt = BATCH_THREADS;  // cells per tile = threads per block
   int lds = 0;             // dynamic LDS reserved per block (caps resident blocks per CU)
+  bool persistent = false; // grid-stride loop over the tiles with a resident grid
+  uint32_t pgrid = 0;      // its grid: resident blocks per CU x CUs, a multiple of 8
 };
 
 namespace lbm {
 
+// Grid of the persistent form: the blocks that fit on the device at once for the current
+// tile size and LDS reserve, rounded down to a multiple of 8 (one per XCD in turn).
+static lbm_status batch_persistent_grid(lbm_batch *b) {
+  const void *fn = batch_sweep_fn(b->s, b->store, b->space, b->reg ? 1 : 0, true);
+  if (!fn) return fail(LBM_EUNSUPPORTED, "no batched sweep kernel for this method");
+  int dev = 0, cus = 0, per_cu = 0;
+  HIPCHECK(hipGetDevice(&dev), "current device");
+  HIPCHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+  HIPCHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, b->bt, size_t(b->lds)), "occupancy");
+  const uint32_t g = uint32_t(std::max(1, per_cu) * std::max(1, cus));
+  b->pgrid = std::max<uint32_t>(8, g - g % 8);
+  return LBM_OK;
+}
+
 static lbm_status batch_one_step(lbm_batch *b) {
-  const void *fn = batch_sweep_fn(b->s, b->store, b->space, b->reg ? 1 : 0);
+  const void *fn = batch_sweep_fn(b->s, b->store, b->space, b->reg ? 1 : 0, b->persistent);
   if (!fn) return fail(LBM_EUNSUPPORTED, "no batched sweep kernel for this method");
   hipError_t e;
   auto go = [&](auto tag) {
@@ -1362,8 +1378,10 @@ static lbm_status batch_one_step(lbm_batch *b) {
     a.tile_box = b->tile_box_d;
     a.relax = static_cast<const Relax<CT> *>(b->relax_d);
     a.swizzle = b->swz;
+    a.ntiles = b->ntiles;
     void *args[] = {&a};
-    return hipLaunchKernel(fn, dim3(b->ntiles), dim3(b->bt), args, size_t(b->lds), b->stream);
+    const unsigned grid = b->persistent ? std::min<unsigned>(b->pgrid, b->ntiles) : b->ntiles;
+    return hipLaunchKernel(fn, dim3(grid), dim3(b->bt), args, size_t(b->lds), b->stream);
   };
   if (b->store == F64) e = go(std::pair<double, double>());
   else if (b->store == F32) e = go(std::pair<float, float>());
@@ -1754,8 +1772,17 @@ extern "C" lbm_status lbm_batch_set_launch(lbm_batch *b, int threads, int swizzl
   batch_clear_graphs(b);
   b->swz = swizzle ? 1 : 0;
   b->lds = lds_bytes;
-  return LBM_OK;
+  return b->persistent ? batch_persistent_grid(b) : LBM_OK;
 }
+
+extern "C" lbm_status lbm_batch_set_persistent(lbm_batch *b, int enable) {
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  batch_clear_graphs(b);
+  b->persistent = enable != 0;
+  return b->persistent ? batch_persistent_grid(b) : LBM_OK;
+}
+
+extern "C" int lbm_batch_get_persistent(const lbm_batch *b) { return b && b->persistent ? 1 : 0; }
 
 extern "C" lbm_status lbm_batch_get_launch(const lbm_batch *b, int *threads, int *swizzle, int *lds_bytes) {
   if (!b || !threads || !swizzle || !lds_bytes) return fail(LBM_EINVAL, "NULL argument");
@@ -1772,43 +1799,46 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
   const int cur0 = b->cur;
   const int64_t t0 = b->t;
   const int bt0 = b->bt, swz0 = b->swz, lds0 = b->lds;
+  const bool pers0 = b->persistent;
   EventPair ev;
   HIPCHECK(ev.create(), "event");
   hipEvent_t e0 = ev.e0, e1 = ev.e1;
   const int reps = 5;
   double best = 1e300;
-  int bb[3] = {bt0, swz0, lds0};
+  int bb[4] = {bt0, swz0, lds0, pers0 ? 1 : 0};
   lbm_status st = LBM_OK;
   for (int bt : {64, 128, 256, 512}) {
     st = batch_build_tiles(b, bt);
-    if (st != LBM_OK) break;
-    for (int swz : {0, 1}) {
-      for (int lds : {0, 16384, 20480, 26624, 32768, 40960, 53248, 65536}) {
-        b->swz = swz;
-        b->lds = lds;
-        for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
-          if (r == 1) (void)hipEventRecord(e0, b->stream);
-          b->cur = cur0;
-          b->t = t0;
-          st = batch_one_step(b);
+    for (int swz : {0, 1})
+      for (int lds : {0, 16384, 20480, 26624, 32768, 40960, 53248, 65536})
+        for (int pers : {0, 1}) {
+          if (st != LBM_OK) break;
+          b->swz = swz;
+          b->lds = lds;
+          b->persistent = pers != 0;
+          if (pers) st = batch_persistent_grid(b);
+          for (int r = 0; r < reps + 1 && st == LBM_OK; ++r) {
+            if (r == 1) (void)hipEventRecord(e0, b->stream);
+            b->cur = cur0;
+            b->t = t0;
+            st = batch_one_step(b);
+          }
+          (void)hipEventRecord(e1, b->stream);
+          (void)hipEventSynchronize(e1);
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (st != LBM_OK) break;
+          if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
+            std::fprintf(stderr, "[lbm batch autotune] threads %d swizzle %d lds %d persistent %d: %.4f ms/step\n", bt,
+                         swz, lds, pers, ms / reps);
+          if (ms < best) {
+            best = ms;
+            bb[0] = bt;
+            bb[1] = swz;
+            bb[2] = lds;
+            bb[3] = pers;
+          }
         }
-        (void)hipEventRecord(e1, b->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (st != LBM_OK) break;
-        if (std::getenv("LBM_AUTOTUNE_VERBOSE"))
-          std::fprintf(stderr, "[lbm batch autotune] threads %d swizzle %d lds %d: %.4f ms/step\n", bt, swz, lds,
-                       ms / reps);
-        if (ms < best) {
-          best = ms;
-          bb[0] = bt;
-          bb[1] = swz;
-          bb[2] = lds;
-        }
-      }
-      if (st != LBM_OK) break;
-    }
     if (st != LBM_OK) break;
   }
   b->cur = cur0;
@@ -1816,6 +1846,8 @@ extern "C" lbm_status lbm_batch_autotune(lbm_batch *b) {
   lbm_status s2 = batch_build_tiles(b, st == LBM_OK ? bb[0] : bt0);
   b->swz = st == LBM_OK ? bb[1] : swz0;
   b->lds = st == LBM_OK ? bb[2] : lds0;
+  b->persistent = st == LBM_OK ? bb[3] != 0 : pers0;
+  if (s2 == LBM_OK && b->persistent) s2 = batch_persistent_grid(b);
   batch_clear_graphs(b);
   return st != LBM_OK ? st : s2;
 }

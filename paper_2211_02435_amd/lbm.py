@@ -116,6 +116,8 @@ SIGNATURES = {
     "lbm_batch_set_launch": (c_int, [c_void_p, c_int, c_int, c_int]),
     "lbm_batch_get_launch": (c_int, [c_void_p, POINTER(c_int), POINTER(c_int), POINTER(c_int)]),
     "lbm_batch_autotune": (c_int, [c_void_p]),
+    "lbm_batch_set_persistent": (c_int, [c_void_p, c_int]),
+    "lbm_batch_get_persistent": (c_int, [c_void_p]),
     "lbm_copy_bandwidth": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, POINTER(c_double)]),
     "lbm_debug_stream_only": (c_int, [c_void_p, c_int64]),
 }
@@ -429,6 +431,12 @@ class Batch:
         t, s, l = c_int(), c_int(), c_int()
         check(self.lib.lbm_batch_get_launch(self.b, ctypes.byref(t), ctypes.byref(s), ctypes.byref(l)))
         return t.value, s.value, l.value
+
+    def lbm_batch_set_persistent(self, enable):
+        check(self.lib.lbm_batch_set_persistent(self.b, 1 if enable else 0))
+
+    def lbm_batch_get_persistent(self):
+        return bool(self.lib.lbm_batch_get_persistent(self.b))
 
     def lbm_batch_autotune(self):
         check(self.lib.lbm_batch_autotune(self.b))
