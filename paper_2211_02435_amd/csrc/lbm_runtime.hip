@@ -1145,7 +1145,11 @@ extern "C" lbm_status lbm_autotune(lbm_ctx *c) {
   if (file && cache_lookup(file, key, &bx, &by, &swz, &vec, &lds) && bx * by <= max_threads) {
     lbm_status s0 = lbm_set_launch(c, bx, by, swz);
     if (s0 == LBM_OK) s0 = apply_variant(mfma ? 0 : vec);
-    return s0 != LBM_OK ? s0 : lbm_set_lds_reserve(c, mfma ? 0 : lds);
+    if (s0 == LBM_OK) s0 = lbm_set_lds_reserve(c, mfma ? 0 : lds);
+    if (s0 == LBM_OK) return LBM_OK;
+    // the cached choice does not apply to this context (e.g. caller buffers without the
+    // alignment the LDS variant needs): tune it afresh
+    g_last_error.clear();
   }
   // candidate shapes: (bx, by, swizzle, variant)
   const bool plain = !mfma && !forced(c) && !c->literal && !c->R.cross;  // the default branch of one_step
