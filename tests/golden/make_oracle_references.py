@@ -24,6 +24,10 @@ Targets (each writes tests/golden/<name>_oracle.npz):
                     generator, amplitude and bump widths, seed 0), 1000 steps: df at 1024
                     sampled cells after 100 steps, velocity and height at 4096 sampled cells
                     after 1000 steps
+  swe4096           the shallow-water workload at its full size, 4096^2, 100 steps: df at 1024
+                    sampled cells, velocity and height at 4096 sampled cells
+  d3q19_raw256      the D3Q19 raw-moment workload at its full size, 256^3, 100 steps: df at
+                    1024 sampled cells, velocity and density at 4096 sampled cells
 
     python tests/golden/make_oracle_references.py [--procs 8] [target ...]
 """
@@ -61,12 +65,12 @@ def _spec(key):
     kind, arg = key
     if kind == "tgv128_cumulant":
         return ("D3Q27", "cumulant", O.regularized_rates("D3Q27", W.re_to_omega(0.05, 512, 1600.0)), {})
-    if kind == "d3q19_raw64":
+    if kind == "d3q19_raw64":  # the D3Q19 method of every D3Q19 target (the 256^3 rates)
         return ("D3Q19", "raw", O.regularized_rates("D3Q19", W.re_to_omega(0.02, 256, 1600.0)), {})
     if kind == "ensemble32":
         b = W.batch_ensemble(256, seed=0)[arg]
         return ("D3Q27", "central", O.regularized_rates("D3Q27", b["omega_shear"]), {})
-    if kind == "swe512":
+    if kind == "swe512":  # the shallow-water method of every shallow-water target
         cfg = W.WORKLOADS["swe_d2q9_4096"]
         return ("D2Q9", "central", O.regularized_rates("D2Q9", cfg["omega_shear"]),
                 {"equilibrium": "swe", "gravity": cfg["gravity"]})
@@ -179,8 +183,33 @@ def make_swe512(pool, procs):
                         df=snap["df100"], u_pts=pts_u, u=u[(slice(None),) + sel].T, h=h[sel])
 
 
+def _full_size(pool, procs, name, key, fields, dims, steps):
+    """df at 1024 and the macroscopic fields at 4096 sampled cells of a full-size workload."""
+    m = method(key)
+    df = O.init_equilibrium(m, *fields)
+    del fields
+    pts_df = W.sample_cells(dims, 1024, seed=16)
+    pts_u = W.sample_cells(dims, 4096, seed=17)
+    df = run(pool, procs, key, df, steps, {}, name)
+    sel = (pts_u[:, 2], pts_u[:, 1], pts_u[:, 0])
+    r, u = O.macroscopic(m, df)
+    np.savez_compressed(os.path.join(HERE, name + "_oracle.npz"), dims=np.array(dims), steps=steps,
+                        df_pts=pts_df, df=_cells_df(df, pts_df), u_pts=pts_u, u=u[(slice(None),) + sel].T,
+                        rho=r[sel])
+
+
+def make_swe4096(pool, procs):
+    n = 4096
+    _full_size(pool, procs, "swe4096", ("swe512", None), W.swe_bumps(n, seed=0), (n, n, 1), 100)
+
+
+def make_d3q19_256(pool, procs):
+    n, u0 = 256, 0.02
+    _full_size(pool, procs, "d3q19_raw256", ("d3q19_raw64", None), W.tgv3d_fields(n, u0=u0), (n, n, n), 100)
+
+
 TARGETS = {"tgv128_cumulant": make_tgv128, "d3q19_raw64": make_d3q19, "ensemble32": make_ensemble32,
-           "swe512": make_swe512}
+           "swe512": make_swe512, "swe4096": make_swe4096, "d3q19_raw256": make_d3q19_256}
 
 
 def main(argv=None):

@@ -9,7 +9,8 @@ Bars (the Taylor-Green configuration of sec. 5.1 and the shallow-water case of s
   FP64 storage: max |df_gpu - df_oracle| <= 1e-12 after 100 steps;
   FP32 storage: relative L2 velocity error <= 1e-5 at the end of the run;
   FP16 storage (shallow water): the velocity error at step 1000 is stated and bounded.
-Relative L2 errors are taken over the sampled cells.
+Relative L2 errors are taken over the sampled cells.  The D3Q19 and shallow-water workloads
+are also checked at their full sizes (256^3, 4096^2) for 100 steps.
 """
 import os
 
@@ -171,3 +172,82 @@ def test_tgv128_populations_at_step_100_against_oracle(storage):
     print("TGV 128^3 %s after %d steps, %d sampled cells: max|d df| = %.3e"
           % (storage, int(ref["df_step"]), len(ref["df_pts"]), err))
     assert err <= (1e-12 if storage == "f64" else 1e-6)
+
+
+# ------------------------------------------------------------------------------------------
+# Two workloads at their full size for 100 steps (the oracle's sampled cells)
+# ------------------------------------------------------------------------------------------
+def _gpu_cells(lat, pts):
+    """df and the macroscopic fields of the sampled cells, gathered on the device."""
+    import torch
+    nx, ny, nz = lat.dims
+    n = nx * ny * nz
+    cells = torch.as_tensor((pts[:, 2] * ny + pts[:, 1]) * nx + pts[:, 0], device="cuda")
+    dev = torch.empty(lat.q * n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lbm.check(lat.lib.lbm_get_populations(lat.ctx, lbm._dptr(dev)))
+    df = dev[torch.arange(lat.q, device="cuda")[None, :] * n + cells[:, None]].cpu().numpy()
+    del dev
+    r = torch.empty(n, dtype=torch.float64, device="cuda")
+    u = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lbm.check(lat.lib.lbm_macroscopic(lat.ctx, lbm._dptr(r), lbm._dptr(u)))
+    uc = u[torch.arange(3, device="cuda")[None, :] * n + cells[:, None]].cpu().numpy()
+    rc = r[cells].cpu().numpy()
+    del r, u
+    torch.cuda.empty_cache()
+    return df, rc, uc
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_d3q19_raw_256_full_size_100_steps_against_oracle(storage):
+    ref = _ref("d3q19_raw256")
+    dims, steps = tuple(int(v) for v in ref["dims"]), int(ref["steps"])
+    cfg = W.WORKLOADS["d3q19_raw_256"]
+    om = lbm.regularized_rates("D3Q19", cfg["omega_shear"])
+    rho, u = W.tgv3d_fields(dims[0], u0=cfg["u0"])
+    lat = lbm.Lattice("D3Q19", "raw", om, dims, storage=storage)
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_autotune()
+    lat.lbm_graph_prepare(steps)
+    lat.lbm_step(steps)
+    df, _, _ = _gpu_cells(lat, ref["df_pts"])
+    _, rg, ug = _gpu_cells(lat, ref["u_pts"])
+    err = float(np.abs(df - ref["df"]).max())
+    rel = _rel(ug, ref["u"])
+    print("D3Q19 raw 256^3 %s, %d steps: max|d df| = %.3e, relative L2 velocity error %.3e, max|d rho| %.3e"
+          % (storage, steps, err, rel, float(np.abs(rg - ref["rho"]).max())))
+    if storage == "f64":
+        assert err <= 1e-12
+        assert rel <= 1e-10
+    else:
+        assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_swe_4096_full_size_100_steps_against_oracle(storage):
+    ref = _ref("swe4096")
+    dims, steps = tuple(int(v) for v in ref["dims"]), int(ref["steps"])
+    cfg = W.WORKLOADS["swe_d2q9_4096"]
+    om = lbm.regularized_rates("D2Q9", cfg["omega_shear"])
+    h, u = W.swe_bumps(dims[0], seed=0)
+    lat = lbm.Lattice("D2Q9", "central", om, dims, storage=storage, equilibrium="swe", gravity=cfg["gravity"])
+    lat.lbm_init_equilibrium(h, u)
+    del h, u
+    lat.lbm_autotune()
+    lat.lbm_step(steps)
+    df, _, _ = _gpu_cells(lat, ref["df_pts"])
+    _, hg, ug = _gpu_cells(lat, ref["u_pts"])
+    err = float(np.abs(df - ref["df"]).max())
+    rel = _rel(ug[:, :2], ref["u"][:, :2])
+    dh = float(np.abs(hg - ref["rho"]).max())
+    print("SWE 4096^2 %s, %d steps: max|d df| = %.3e, relative L2 velocity error %.3e, max|d h| %.3e"
+          % (storage, steps, err, rel, dh))
+    if storage == "f64":
+        assert err <= 1e-12
+        assert rel <= 1e-10
+    else:
+        # FP16 storage after 100 steps (the 512^2 instance: 1.6e-3 in df at step 100)
+        assert err <= 5e-3
+        assert rel <= 5e-2
