@@ -220,3 +220,28 @@ def test_nonperiodic_rejected():
     p = _p()
     p.periodic[2] = 0
     assert lbm.lbm_validate(p) == lbm.LBM_EUNSUPPORTED
+
+
+def test_null_handles_are_rejected_without_a_device():
+    """Every context and batch entry point checks its handle before touching a device."""
+    import ctypes
+    lib = lbm.load()
+    EINVAL = -1
+    out = (ctypes.c_double * 6)()
+    assert lib.lbm_diagnostics_noalloc(None, out) == EINVAL
+    assert lib.lbm_diagnostics(None, out) == EINVAL
+    assert lib.lbm_set_staged(None, 1) == EINVAL
+    assert lib.lbm_get_staged(None) == 0
+    assert lib.lbm_set_vectorized(None, 1) == EINVAL
+    assert lib.lbm_step(None, 3) == EINVAL
+    assert lib.lbm_graph_prepare(None, 3) == EINVAL
+    assert lib.lbm_autotune(None) == EINVAL
+    ms = ctypes.c_double()
+    assert lib.lbm_time_steps(None, 2, ctypes.byref(ms)) == EINVAL
+    assert lib.lbm_batch_set_persistent(None, 1) == EINVAL
+    assert lib.lbm_batch_get_persistent(None) == 0
+    assert lib.lbm_batch_step(None, 2) == EINVAL
+    assert lib.lbm_batch_autotune(None) == EINVAL
+    assert lib.lbm_batch_time_steps(None, 2, ctypes.byref(ms)) == EINVAL
+    assert lib.lbm_copy_bandwidth(None, None, 16, 1, None, ctypes.byref(ms)) == EINVAL
+    assert lbm.last_error()
