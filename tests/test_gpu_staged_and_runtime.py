@@ -95,6 +95,30 @@ def test_aa_shifted_odd_step_matches_per_cell_kernel_and_oracle(stencil, space, 
             assert err <= 1e-13, err
 
 
+@pytest.mark.parametrize("stencil,space", [("D3Q27", "cumulant"), ("D2Q9", "central")])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_lds_variants_in_the_planes_layout(stencil, space, storage, streaming):
+    """Both LDS variants with one population plane per population (padded plane stride)."""
+    dims = (256, 6, 3) if stencil != "D2Q9" else (256, 9, 1)
+    om = O.regularized_rates(stencil, 1.7, omega_bulk=1.2)
+    m = O.Method(stencil, space, om)
+    df0 = _state(m, dims, seed=8)
+    out = {}
+    for staged in (False, True):
+        lat = lbm.Lattice(stencil, space, om, dims, storage=storage, streaming=streaming, layout="planes")
+        assert lat.lbm_get_layout() == "planes"
+        lat.lbm_set_launch(128, 1, 1)
+        lat.lbm_set_staged(staged)
+        lat.lbm_set_populations(df0)
+        lat.lbm_step(5)
+        out[staged] = lat.lbm_get_populations()
+        lat.close()
+    assert np.array_equal(out[True], out[False])
+    if storage == "f64":
+        assert np.abs(out[True] - O.step(m, df0, 5)).max() <= 1e-13
+
+
 def test_staged_shallow_water_and_stream_only():
     om = O.regularized_rates("D2Q9", 0.695652)
     h, u = W.swe_bumps(256, seed=0)
