@@ -38,3 +38,18 @@ def test_traffic_hash_covers_runtime_and_build_flags():
     for needed in ("paper_2211_02435_amd/csrc/lbm_runtime.hip", "paper_2211_02435_amd/csrc/lbm_instantiate.inc",
                    "paper_2211_02435_amd/csrc/k_d3q27_f32.hip", "paper_2211_02435_amd/build.py"):
         assert needed in files
+
+
+def test_cpu_baseline_record_on_a_tiny_sample():
+    """The oracle legs of the CPU baseline (all usable cores, one core, the D2Q9 run) on tiny
+    copies: the record carries every field the bench line states."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import lbm_workloads as W
+    r = bench.cpu_baseline(W.WORKLOADS["d3q27_cumulant_512"], n_all=8, steps_all=1, n_one=6, steps_one=1,
+                           d2q9_steps=2)
+    assert r["kind"] == "oracle" and r["unit"] == "MLUPS" and r["value"] > 0
+    assert 1 <= r["cores"] <= 16
+    assert r["single_core"]["cores"] == 1 and r["single_core"]["value"] > 0
+    assert r["d2q9_central_64"]["value"] > 0
+    assert r["cpu_model"] and r["nproc"] >= 1 and r["usable_cores"] >= 1
