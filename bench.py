@@ -220,6 +220,59 @@ def oracle_accuracy(lbm, cfg):
     return out
 
 
+FULL_SIZE_REFERENCES = {"d3q19_raw_256": "d3q19_raw256", "swe_d2q9_4096": "swe4096"}
+
+
+def full_size_accuracy(lbm, name, cfg, storages, fields, dims):
+    """Outside the timed region: the workload at its full size, run for as many steps as the
+    FP64 oracle's reference (tests/golden/<ref>_oracle.npz, written from the oracle alone) in
+    every storage of the line, compared at the reference's sampled cells: max |d df| and the
+    relative L2 error of the velocity (in-plane for the 2-D workload)."""
+    import torch
+    ref_name = FULL_SIZE_REFERENCES.get(name)
+    path = ref_name and os.path.join(ROOT, "tests", "golden", ref_name + "_oracle.npz")
+    if not path or not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    if tuple(int(v) for v in ref["dims"]) != tuple(dims):
+        return None
+    steps = int(ref["steps"])
+    nx, ny, nz = dims
+    n = nx * ny * nz
+    d = 2 if cfg["stencil"] == "D2Q9" else 3
+    kw = {"equilibrium": "swe", "gravity": cfg["gravity"]} if cfg.get("equilibrium") == "swe" else {}
+    out = {"steps": steps, "df_cells": int(len(ref["df_pts"])), "velocity_cells": int(len(ref["u_pts"]))}
+
+    def cells(pts):
+        return torch.as_tensor((pts[:, 2] * ny + pts[:, 1]) * nx + pts[:, 0], device="cuda")
+
+    for st in storages:
+        lat = lbm.Lattice(cfg["stencil"], cfg["space"], workload_rates(cfg), dims, storage=st, **kw)
+        lat.lbm_init_equilibrium(*fields)
+        lat.lbm_autotune()
+        lat.lbm_step(steps)
+        q = lat.q
+        dev = torch.empty(q * n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        lbm.check(lat.lib.lbm_get_populations(lat.ctx, lbm._dptr(dev)))
+        c = cells(ref["df_pts"])
+        df = dev[torch.arange(q, device="cuda")[None, :] * n + c[:, None]].cpu().numpy()
+        del dev
+        r = torch.empty(n, dtype=torch.float64, device="cuda")
+        u = torch.empty(3 * n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        lbm.check(lat.lib.lbm_macroscopic(lat.ctx, lbm._dptr(r), lbm._dptr(u)))
+        c = cells(ref["u_pts"])
+        uc = u[torch.arange(d, device="cuda")[None, :] * n + c[:, None]].cpu().numpy()
+        del r, u
+        lat.close()
+        torch.cuda.empty_cache()
+        want = ref["u"][:, :d]
+        out[st] = {"max_abs_df_vs_oracle": float(np.abs(df - ref["df"]).max()),
+                   "velocity_rel_l2_vs_oracle": float(np.linalg.norm(uc - want) / np.linalg.norm(want))}
+    return out
+
+
 _ORACLE_METHODS = {}
 
 
@@ -391,6 +444,7 @@ def main():
         return
 
     fields, dims = workload_fields(name, cfg, n)
+    full_accuracy = None
     storages = {"swe_d2q9_4096": ["f16", "f64"], "d2q9_central_64": ["f64"]}.get(name, ["f32", "f64"])
     if args.no_fp64:
         storages = [s for s in storages if s != "f64"] or storages[:1]
@@ -405,6 +459,10 @@ def main():
         runs[st], lats[st] = res, lat
         print("[bench] %s: %.0f MLUPS, %.1f GB/s" % (st, res["mlups"], res["achieved_GBps"]),
               file=sys.stderr, flush=True)
+    if not args.no_accuracy and name in FULL_SIZE_REFERENCES and args.streaming == "pull" \
+            and args.transform == "chimera" and args.rates == "regularized":
+        full_accuracy = full_size_accuracy(lbm, name, cfg, storages, fields, dims)
+        print("[bench] accuracy vs oracle: %s" % json.dumps(full_accuracy), file=sys.stderr, flush=True)
     del fields
     main_st = storages[0]
     vel = None
@@ -462,6 +520,7 @@ def main():
         "fp64": runs.get("f64") if main_st != "f64" else None,
         "velocity_rel_l2_vs_fp64": vel,
         "vs_oracle_128_copy": accuracy,
+        "vs_oracle_full_size": full_accuracy,
         "batched": batch,
         "copy_ceiling_GBps": ceiling,
         "cpu_baseline": cpu,
