@@ -28,6 +28,9 @@ Targets (each writes tests/golden/<name>_oracle.npz):
                     sampled cells, velocity and height at 4096 sampled cells
   d3q19_raw256      the D3Q19 raw-moment workload at its full size, 256^3, 100 steps: df at
                     1024 sampled cells, velocity and density at 4096 sampled cells
+  swe1024           a 1024^2 instance of the shallow-water workload (as swe512), over the
+                    workload's full length of 1000 steps: df at 1024 sampled cells after 100
+                    steps, velocity and height at 4096 sampled cells after 1000 steps
 
     python tests/golden/make_oracle_references.py [--procs 8] [target ...]
 """
@@ -166,21 +169,30 @@ def make_ensemble32(pool, procs):
     np.savez_compressed(os.path.join(HERE, "ensemble32_oracle.npz"), **out)
 
 
-def make_swe512(pool, procs):
-    n, steps = 512, 1000
+def _swe_instance(pool, procs, n, seeds):
+    """An n x n instance of the shallow-water workload over its 1000 steps."""
+    steps = 1000
     key = ("swe512", None)
     m = method(key)
     h, u = W.swe_bumps(n, seed=0)
     df = O.init_equilibrium(m, h, u)
-    pts_df = W.sample_cells((n, n, 1), 1024, seed=14)
-    pts_u = W.sample_cells((n, n, 1), 4096, seed=15)
+    pts_df = W.sample_cells((n, n, 1), 1024, seed=seeds[0])
+    pts_u = W.sample_cells((n, n, 1), 4096, seed=seeds[1])
     snap = {}
     df = run(pool, procs, key, df, steps, {100: lambda d: snap.__setitem__("df100", _cells_df(d, pts_df))},
-             "swe512")
+             "swe%d" % n)
     h, u = O.macroscopic(m, df)
     sel = (pts_u[:, 2], pts_u[:, 1], pts_u[:, 0])
-    np.savez_compressed(os.path.join(HERE, "swe512_oracle.npz"), n=n, steps=steps, df_step=100, df_pts=pts_df,
-                        df=snap["df100"], u_pts=pts_u, u=u[(slice(None),) + sel].T, h=h[sel])
+    np.savez_compressed(os.path.join(HERE, "swe%d_oracle.npz" % n), n=n, steps=steps, df_step=100,
+                        df_pts=pts_df, df=snap["df100"], u_pts=pts_u, u=u[(slice(None),) + sel].T, h=h[sel])
+
+
+def make_swe512(pool, procs):
+    _swe_instance(pool, procs, 512, (14, 15))
+
+
+def make_swe1024(pool, procs):
+    _swe_instance(pool, procs, 1024, (18, 19))
 
 
 def _full_size(pool, procs, name, key, fields, dims, steps):
@@ -209,7 +221,8 @@ def make_d3q19_256(pool, procs):
 
 
 TARGETS = {"tgv128_cumulant": make_tgv128, "d3q19_raw64": make_d3q19, "ensemble32": make_ensemble32,
-           "swe512": make_swe512, "swe4096": make_swe4096, "d3q19_raw256": make_d3q19_256}
+           "swe512": make_swe512, "swe4096": make_swe4096, "d3q19_raw256": make_d3q19_256,
+           "swe1024": make_swe1024}
 
 
 def main(argv=None):
