@@ -121,10 +121,11 @@ def test_ensemble_boxes_graph_against_oracle(storage):
 
 
 # ------------------------------------------------------------------------------------------
-# Shallow water: a 512^2 instance of the 16-bump workload, 1000 steps
+# Shallow water: 512^2 and 1024^2 instances of the 16-bump workload, 1000 steps
 # ------------------------------------------------------------------------------------------
-def test_swe_512_against_oracle():
-    ref = _ref("swe512")
+@pytest.mark.parametrize("name", ["swe512", "swe1024"])
+def test_swe_instance_against_oracle(name):
+    ref = _ref(name)
     n, steps, k100 = int(ref["n"]), int(ref["steps"]), int(ref["df_step"])
     cfg = W.WORKLOADS["swe_d2q9_4096"]
     om = lbm.regularized_rates("D2Q9", cfg["omega_shear"])
@@ -144,8 +145,8 @@ def test_swe_512_against_oracle():
         rel = _rel(_u_at(ug[:2], pts), ref["u"][:, :2])
         dh = float(np.abs(hg[pts[:, 2], pts[:, 1], pts[:, 0]] - ref["h"]).max())
         out[storage] = (err_df, rel, dh)
-        print("SWE 512^2 %s: max|d df| at step %d = %.3e; step %d: relative L2 velocity error %.3e, "
-              "max|d h| %.3e" % (storage, k100, err_df, steps, rel, dh))
+        print("SWE %d^2 %s: max|d df| at step %d = %.3e; step %d: relative L2 velocity error %.3e, "
+              "max|d h| %.3e" % (n, storage, k100, err_df, steps, rel, dh))
     assert out["f64"][0] <= 1e-12
     assert out["f64"][1] <= 1e-10
     assert out["f64"][2] <= 1e-12
