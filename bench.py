@@ -220,6 +220,42 @@ def oracle_accuracy(lbm, cfg):
     return out
 
 
+def swe_instance_accuracy(lbm, cfg, storages, name="swe1024"):
+    """Outside the timed region: an n x n instance of the shallow-water workload (same
+    generator, rates and gravity) over the workload's 1000 steps in every storage of the line,
+    against the FP64 oracle's values at sampled cells (tests/golden/<name>_oracle.npz, written
+    from the oracle alone): max |d df| after 100 steps, the relative L2 error of the in-plane
+    velocity and max |d h| after 1000 steps."""
+    path = os.path.join(ROOT, "tests", "golden", name + "_oracle.npz")
+    if not os.path.exists(path):
+        return None
+    ref = np.load(path)
+    n, k1, k2 = int(ref["n"]), int(ref["df_step"]), int(ref["steps"])
+    h, u = W.swe_bumps(n, seed=0)
+    pts, upts = ref["df_pts"], ref["u_pts"]
+    sel = (upts[:, 2], upts[:, 1], upts[:, 0])
+    out = {"instance": "%d^2, 16 bumps, seed 0" % n, "df_step": k1, "velocity_step": k2,
+           "df_cells": int(len(pts)), "velocity_cells": int(len(upts))}
+    for st in storages:
+        lat = lbm.Lattice(cfg["stencil"], cfg["space"], workload_rates(cfg), (n, n, 1), storage=st,
+                          equilibrium="swe", gravity=cfg["gravity"])
+        lat.lbm_init_equilibrium(h, u)
+        lat.lbm_autotune()
+        lat.lbm_step(k1)
+        df = lat.lbm_get_populations()
+        err = float(np.abs(df[:, pts[:, 2], pts[:, 1], pts[:, 0]].T - ref["df"]).max())
+        del df
+        lat.lbm_step(k2 - k1)
+        hg, ug = lat.lbm_macroscopic()
+        lat.close()
+        want = ref["u"][:, :2]
+        got = ug[(slice(0, 2),) + sel].T
+        out[st] = {"max_abs_df_vs_oracle": err,
+                   "velocity_rel_l2_vs_oracle": float(np.linalg.norm(got - want) / np.linalg.norm(want)),
+                   "max_abs_dh_vs_oracle": float(np.abs(hg[sel] - ref["h"]).max())}
+    return out
+
+
 FULL_SIZE_REFERENCES = {"d3q19_raw_256": "d3q19_raw256", "swe_d2q9_4096": "swe4096"}
 
 
@@ -444,7 +480,7 @@ def main():
         return
 
     fields, dims = workload_fields(name, cfg, n)
-    full_accuracy = None
+    full_accuracy = swe_accuracy = None
     storages = {"swe_d2q9_4096": ["f16", "f64"], "d2q9_central_64": ["f64"]}.get(name, ["f32", "f64"])
     if args.no_fp64:
         storages = [s for s in storages if s != "f64"] or storages[:1]
@@ -463,6 +499,10 @@ def main():
             and args.transform == "chimera" and args.rates == "regularized":
         full_accuracy = full_size_accuracy(lbm, name, cfg, storages, fields, dims)
         print("[bench] accuracy vs oracle: %s" % json.dumps(full_accuracy), file=sys.stderr, flush=True)
+        if name == "swe_d2q9_4096":
+            swe_accuracy = swe_instance_accuracy(lbm, cfg, storages)
+            print("[bench] accuracy vs oracle, 1000 steps: %s" % json.dumps(swe_accuracy), file=sys.stderr,
+                  flush=True)
     del fields
     main_st = storages[0]
     vel = None
@@ -521,6 +561,7 @@ def main():
         "velocity_rel_l2_vs_fp64": vel,
         "vs_oracle_128_copy": accuracy,
         "vs_oracle_full_size": full_accuracy,
+        "vs_oracle_1024_instance_1000_steps": swe_accuracy,
         "batched": batch,
         "copy_ceiling_GBps": ceiling,
         "cpu_baseline": cpu,

@@ -12,7 +12,7 @@
   python -m paper_2211_02435_amd.rocprof_summary counters <db> [<db> ...] [--match sweep]
       median value per dispatch of every PMC counter in the databases, per kernel
 
-  python -m paper_2211_02435_amd.rocprof_summary memory <db> [<db> ...] --copy-bytes <bytes>
+  python -m paper_2211_02435_amd.rocprof_summary memory <db> [<db> ...] (--copy-bytes <bytes> | --scales F,W)
       the memory-interface view of every sweep and copy kernel from the passes FETCH_SIZE;
       WRITE_SIZE; TCC_EA0_{RD,WR}REQ{,_LEVEL}_sum with GRBM_GUI_ACTIVE;
       TCC_EA0_WRREQ_64B_sum, TCC_EA0_WRREQ_STALL_sum, TCC_EA0_{RD,WR}REQ_DRAM_CREDIT_STALL_sum
@@ -127,14 +127,19 @@ XCDS = 8           # GRBM_GUI_ACTIVE is summed over the XCDs
 TCC_CHANNELS = 128  # the _sum counters are summed over 16 L2 channels on each of the 8 XCDs
 
 
-def memory_view(dbs, copy_bytes, clock_ghz=2.1):
-    """Derived memory-interface figures per kernel (see the module docstring)."""
+def memory_view(dbs, copy_bytes=None, clock_ghz=2.1, scales=None):
+    """Derived memory-interface figures per kernel (see the module docstring).  FETCH_SIZE and
+    WRITE_SIZE are scaled by the copy kernel of copy_bytes each way in the same databases, or,
+    for runs without it, by the given (fetch, write) factors."""
     t = counters_table(dbs)
     copy = [v for k, v in t.items() if "copy_kernel" in k]
-    if not copy:
-        raise SystemExit("no copy_kernel dispatch to scale FETCH_SIZE / WRITE_SIZE")
-    sf = copy_bytes / (copy[0]["FETCH_SIZE"] * 1024.0)
-    sw = copy_bytes / (copy[0]["WRITE_SIZE"] * 1024.0)
+    if copy and copy_bytes:
+        sf = copy_bytes / (copy[0]["FETCH_SIZE"] * 1024.0)
+        sw = copy_bytes / (copy[0]["WRITE_SIZE"] * 1024.0)
+    elif scales:
+        sf, sw = scales
+    else:
+        raise SystemExit("no copy_kernel dispatch (with --copy-bytes) or --scales to scale FETCH_SIZE / WRITE_SIZE")
     out = []
     for k, v in t.items():
         if not ("sweep" in k or "copy_kernel" in k):
@@ -198,7 +203,9 @@ def main(argv=None):
     c.add_argument("--match", default=None)
     m = sub.add_parser("memory")
     m.add_argument("dbs", nargs="+")
-    m.add_argument("--copy-bytes", type=float, required=True)
+    m.add_argument("--copy-bytes", type=float, default=None)
+    m.add_argument("--scales", default=None,
+                   help="fetch,write factors for databases without the copy kernel (e.g. 2,1 on gfx950)")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         rows = stats(a.db, a.match, a.last)
@@ -210,7 +217,8 @@ def main(argv=None):
         print("%-72s %7s %7s %5s %5s %5s %7s %6s %7s %7s %6s %6s %7s" % (
             "kernel", "rd GB", "wr GB", "B/rd", "B/wr", "wr64", "rd lat", "wr lat", "rd fly", "wr fly",
             "wstall", "rcred", "busy ms"))
-        for r in memory_view(a.dbs, a.copy_bytes):
+        scales = tuple(float(v) for v in a.scales.split(",")) if a.scales else None
+        for r in memory_view(a.dbs, a.copy_bytes, scales=scales):
             print("%-72s %7.2f %7.2f %5.0f %5.0f %5.2f %7.0f %6.0f %7.0f %7.0f %6.3f %6.3f %7.3f" % (
                 r["kernel"][:72], r["fetch_GB"], r["write_GB"], r["bytes_per_read_req"], r["bytes_per_write_req"],
                 r["write_64B_fraction"], r["read_latency_cycles"], r["write_latency_cycles"], r["reads_in_flight"],

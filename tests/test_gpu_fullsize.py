@@ -85,6 +85,44 @@ def test_d3q27_cumulant_512_three_steps_sampled(storage, streaming, tol):
     assert err <= tol
 
 
+def test_d3q27_512_streaming_only_sweeps_move_populations_exactly():
+    """The pull index maps at the metric size in the metric launch (blocks of 256 x 1 threads,
+    XCD order, 53248 bytes of LDS reserved, rows layout, FP32): 20 sweeps with the collision
+    replaced by the identity (lbm_debug_stream_only) must leave df_i(x, 20) = df_i(x - 20 xi_i, 0)
+    bit for bit at every sampled cell, box faces and corners included."""
+    import torch
+    cfg = W.WORKLOADS["d3q27_cumulant_512"]
+    n = cfg["dims"][0]
+    steps = 20
+    om = O.regularized_rates("D3Q27", cfg["omega_shear"])
+    rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
+    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, n), storage="f32")
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_set_launch(256, 1, 1)
+    lat.lbm_set_lds_reserve(53248)
+    pts = W.sample_cells((n, n, n), 512, seed=8)
+    c = np.asarray(O.stencil("D3Q27").xi, dtype=np.int64)  # (q, 3)
+    # source cell of population i of every sampled cell, steps cells upstream
+    src = (pts[:, None, :] - steps * c[None, :, :]) % n  # (m, q, 3)
+    ncell = n ** 3
+    idx0 = torch.as_tensor(np.arange(lat.q)[None, :] * ncell + (src[..., 2] * n + src[..., 1]) * n + src[..., 0],
+                           device="cuda")
+    dev = torch.empty(lat.q * ncell, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lbm.check(lat.lib.lbm_get_populations(lat.ctx, lbm._dptr(dev)))
+    want = dev[idx0].cpu().numpy()
+    del dev
+    torch.cuda.empty_cache()
+    lat.lbm_debug_stream_only(steps)
+    got = _gpu_samples(lat, pts)
+    lat.close()
+    mism = int((got != want).sum())
+    print("D3Q27 512^3 FP32, %d streaming-only sweeps, %d sampled cells: %d mismatches"
+          % (steps, len(pts), mism))
+    assert mism == 0
+
+
 @pytest.mark.parametrize("storage,tol", [("f32", 2e-8), ("f64", 1e-15)])
 def test_d3q27_cumulant_512_general_rates_sampled(storage, tol):
     """The general-rate kernel at full size (every rate of order >= 3 set to 1.3, so no

@@ -67,3 +67,17 @@ def test_memory_view_applies_littles_law(tmp_path):
     assert s["reads_in_flight"] == pytest.approx(5000.0)
     assert s["write_stall_fraction"] == pytest.approx(0.01)
     assert COPY in view
+
+
+def test_memory_view_takes_given_scales_without_a_copy_kernel(tmp_path):
+    vals = {"FETCH_SIZE": 1000.0, "WRITE_SIZE": 3000.0, "TCC_EA0_RDREQ_sum": 16.0, "TCC_EA0_RDREQ_LEVEL_sum": 1.0,
+            "TCC_EA0_WRREQ_sum": 48.0, "TCC_EA0_WRREQ_LEVEL_sum": 1.0, "TCC_EA0_WRREQ_64B_sum": 48.0,
+            "TCC_EA0_WRREQ_STALL_sum": 0.0, "TCC_EA0_RDREQ_DRAM_CREDIT_STALL_sum": 0.0,
+            "TCC_EA0_WRREQ_DRAM_CREDIT_STALL_sum": 0.0, "GRBM_GUI_ACTIVE": 8.0}
+    db = _db(str(tmp_path / "s.db"), [(SWEEP, 2, k, v) for k, v in vals.items()])
+    with pytest.raises(SystemExit):
+        R.memory_view([db], None)
+    s = R.memory_view([db], None, scales=(2.0, 1.0))[0]
+    assert s["fetch_GB"] == pytest.approx(1000.0 * 1024 * 2 / 1e9)
+    assert s["write_GB"] == pytest.approx(3000.0 * 1024 / 1e9)
+    assert s["bytes_per_read_req"] == pytest.approx(1000.0 * 1024 * 2 / 16)
