@@ -117,6 +117,12 @@ def test_layout_enum_checked_and_large_boxes_accepted():
         lbm.lbm_required_bytes(_p(dims=(10, 6, 4), storage="f32", streaming="pull"))
     # one population plane beyond 4 GiB is fine: population bases are 64-bit scalars
     assert lbm.lbm_validate(_p(dims=(2048, 2048, 256), storage="f32", layout="planes")) == 0
+    # the largest rows z-planes below 4 GiB (x padded to 256 bytes) pass; one more row is refused
+    assert lbm.lbm_validate(_p(dims=(6250, 6340, 2), storage="f32", layout="rows")) == 0
+    assert lbm.lbm_validate(_p(dims=(6250, 6341, 2), storage="f32", layout="rows")) == lbm.LBM_EUNSUPPORTED
+    assert lbm.lbm_validate(_p(dims=(4420, 4470, 2), storage="f64", layout="rows")) == 0
+    assert lbm.lbm_validate(_p(dims=(4420, 4471, 2), storage="f64", layout="rows")) == lbm.LBM_EUNSUPPORTED
+    assert lbm.lbm_validate(_p(dims=(6250, 6341, 2), storage="f32", layout="auto")) == 0
     # a rows z-plane of 29 GiB is refused, but AUTO falls back to planes (1 GiB z-planes)
     assert lbm.lbm_validate(_p(dims=(65536, 4096, 2), storage="f32", layout="rows")) == lbm.LBM_EUNSUPPORTED
     assert lbm.lbm_validate(_p(dims=(65536, 4096, 2), storage="f32", layout="auto")) == 0

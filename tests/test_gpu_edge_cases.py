@@ -8,6 +8,9 @@
 * The rest state (df = 0) and the shallow-water lake at rest are exact fixed points in every
   precision (bit-exact zero after 50 steps); a uniform flow stays bit-identical across cells
   and at its equilibrium.
+* The largest z-plane the 32-bit lane offsets admit: boxes whose z-plane of population
+  storage sits just under 4 GiB (rows layout, FP32 and FP64, ragged x), two steps of pull and
+  of AA, sampled against the oracle (one- and two-step bars of the full-size tests).
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 5 steps from a non-equilibrium state.
 """
@@ -16,6 +19,7 @@ import pytest
 
 import lbm_workloads as W
 import oracle as O
+import sampled_oracle as SO
 from paper_2211_02435_amd import lbm
 
 pytestmark = pytest.mark.gpu
@@ -169,4 +173,47 @@ def test_uniform_flow_stays_uniform_and_at_equilibrium(space, storage, tol, stre
     want = O.init_equilibrium(m, np.full((1, 1, 1), 1.01), u0[:, None, None, None]).reshape(st.q)
     err = np.abs(df[:, 0] - want).max()
     print("uniform flow %s %s %s: max|df - df_eq| = %.3e" % (space, storage, streaming, err))
+    assert err <= tol
+
+
+# (storage, dims, bar after two steps): the rows layout pads x to 256 bytes, so the z-plane of
+# D3Q27 populations is ny * 27 * nxp * sizeof(storage) bytes, nxp = 6272 (F32) or 4448 (F64);
+# one more row along y would reach 4 GiB and is refused (tests/test_abi_cpu.py)
+LARGEST_PLANE = [("f32", (6250, 6340, 2), 4e-8), ("f64", (4420, 4470, 2), 2e-15)]
+
+
+@pytest.mark.parametrize("storage,dims,tol", LARGEST_PLANE)
+@pytest.mark.parametrize("streaming", ["pull", "aa"])
+def test_largest_z_plane_two_steps_sampled(storage, dims, tol, streaming):
+    import torch
+    nx, ny, nz = dims
+    esize = 4 if storage == "f32" else 8
+    align = 256 // esize
+    nxp = (nx + align - 1) // align * align
+    plane = ny * 27 * nxp * esize
+    assert 0.9999 * 2 ** 32 < plane < 2 ** 32 - 1
+    u0 = 0.05
+    om = O.regularized_rates("D3Q27", 1.9)
+    rho, u = W.tgv3d_fields(nx, ny, nz, u0=u0, period=nx)
+    lat = lbm.Lattice("D3Q27", "cumulant", om, dims, storage=storage, streaming=streaming, layout="rows")
+    assert lat.lbm_get_layout() == "rows"
+    lat.lbm_init_equilibrium(rho, u)
+    del rho, u
+    lat.lbm_set_launch(256, 1, 1)
+    lat.lbm_step(2)
+    pts = W.sample_cells(dims, 48, seed=9)
+    n = nx * ny * nz
+    dev = torch.empty(27 * n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    lbm.check(lat.lib.lbm_get_populations(lat.ctx, lbm._dptr(dev)))
+    cells = torch.as_tensor((pts[:, 2] * ny + pts[:, 1]) * nx + pts[:, 0], device="cuda")
+    got = dev[torch.arange(27, device="cuda")[None, :] * n + cells[:, None]].cpu().numpy()
+    del dev
+    lat.close()
+    torch.cuda.empty_cache()
+    m = O.Method("D3Q27", "cumulant", om)
+    want = SO.k_step_samples(m, pts, dims, lambda x, y, z: W.tgv3d_points(x, y, z, nx, u0), 2)
+    err = float(np.abs(got - want).max())
+    print("D3Q27 %s %s, z-plane of %d bytes, two steps, %d sampled cells: max|d df| = %.3e"
+          % (storage, dims, plane, len(pts), err))
     assert err <= tol
