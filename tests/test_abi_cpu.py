@@ -251,3 +251,13 @@ def test_null_handles_are_rejected_without_a_device():
     assert lib.lbm_batch_time_steps(None, 2, ctypes.byref(ms)) == EINVAL
     assert lib.lbm_copy_bandwidth(None, None, 16, 1, None, ctypes.byref(ms)) == EINVAL
     assert lbm.last_error()
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    """No fallback: with the shared library absent every call raises instead of computing."""
+    monkeypatch.setattr(lbm, "_lib", None)
+    monkeypatch.setattr(lbm, "LIB_PATH", str(tmp_path / "libpaper_lbm.so"))
+    with pytest.raises(RuntimeError, match="not found"):
+        lbm.load()
+    with pytest.raises(RuntimeError, match="not found"):
+        lbm.Lattice("D3Q27", "cumulant", O.regularized_rates("D3Q27", 1.9), (8, 8, 8))
