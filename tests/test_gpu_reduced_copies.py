@@ -84,7 +84,7 @@ def test_d3q19_raw_64_copy_against_oracle(storage):
 # of up to 2^-11 = 4.9e-4 each step.  The velocity is a sum of such deviations divided by rho;
 # its error stays of the order of that unit roundoff relative to u0, times the growth over the
 # run's few hundred steps.  Bar: 1e-2 relative L2; measured 6.4e-4 (D3Q27 cumulant 128^3,
-# 200 steps) and 1.0e-3 (D3Q19 raw 64^3, 500 steps).
+# 200 steps), 1.0e-3 (D3Q19 raw 64^3, 500 steps) and at most 2.4e-4 (ensemble boxes, 100 steps).
 F16_VELOCITY_BAR = 1e-2
 
 
@@ -115,7 +115,7 @@ def test_tgv128_fp16_storage_against_oracle():
 # Ensemble: four edge-32 boxes of the seed-0 ensemble (their own u0, phase and omega_s) in a
 # batch with four boxes of other edges, 100 steps replayed from one recorded graph
 # ------------------------------------------------------------------------------------------
-@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
 def test_ensemble_boxes_graph_against_oracle(storage):
     ref = _ref("ensemble32")
     steps = int(ref["steps"])
@@ -150,8 +150,10 @@ def test_ensemble_boxes_graph_against_oracle(storage):
     if storage == "f64":
         assert worst_df <= 1e-12
         assert worst_rel <= 1e-10
-    else:
+    elif storage == "f32":
         assert worst_rel <= 1e-5
+    else:
+        assert worst_rel <= F16_VELOCITY_BAR
 
 
 # ------------------------------------------------------------------------------------------
