@@ -261,3 +261,41 @@ def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
         lbm.load()
     with pytest.raises(RuntimeError, match="not found"):
         lbm.Lattice("D3Q27", "cumulant", O.regularized_rates("D3Q27", 1.9), (8, 8, 8))
+
+
+def test_plain_c_program_links_and_validates(tmp_path):
+    """A C99 program includes lbm.h, links libpaper_lbm.so and runs the host-only calls
+    (defaults, validation with its error text, required bytes) without a GPU."""
+    src = tmp_path / "use.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include "lbm.h"
+int main(void) {
+  lbm_params p;
+  double om[27];
+  size_t bytes = 0;
+  int i;
+  if (lbm_params_default(&p) != LBM_OK) return 1;
+  for (i = 0; i < 27; ++i) om[i] = 1.0;
+  om[4] = om[5] = om[6] = om[7] = om[8] = 1.9;
+  p.omegas = om;
+  p.n_omegas = 27;
+  p.nx = 64; p.ny = 32; p.nz = 16;
+  if (lbm_validate(&p) != LBM_OK) return 2;
+  if (lbm_required_bytes(&p, &bytes) != LBM_OK) return 3;
+  printf("bytes %zu\n", bytes);
+  p.n_omegas = 19;
+  if (lbm_validate(&p) != LBM_EINVAL) return 4;
+  printf("error %s\n", lbm_last_error());
+  return 0;
+}
+''')
+    exe = tmp_path / "use"
+    libdir = os.path.dirname(lbm.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe),
+                    "-L", libdir, "-lpaper_lbm", "-Wl,-rpath," + libdir], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr)
+    lines = dict(l.split(" ", 1) for l in r.stdout.splitlines())
+    assert int(lines["bytes"]) == lbm.lbm_required_bytes(_p(dims=(64, 32, 16), storage="f32"))
+    assert lines["error"] != ""
