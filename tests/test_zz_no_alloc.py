@@ -81,3 +81,31 @@ def test_noalloc_diagnostics_report_nonfinite_populations():
     assert st == lbm.LBM_ENONFINITE and out[5] == 2.0
     st = lat.lib.lbm_diagnostics_noalloc(lat.ctx, None)
     assert st == -1
+
+
+def test_noalloc_diagnostics_captured_in_a_caller_graph():
+    """The caller this entry point is for: a HIP graph captured (here by torch) on the
+    context's stream holds the two reduction kernels; every replay, with eager sweeps, another
+    context's call on the same scratch array and synchronisations in between, gives
+    lbm_diagnostics' result for the current state."""
+    import torch
+    lat, _ = _ctx("D3Q27", "cumulant", (70, 9, 5), "f32", seed=11)
+    other, _ = _ctx("D3Q19", "raw", (40, 12, 10), "f64", seed=13)
+    lat.lbm_set_graphs(False)
+    out = torch.full((6,), float("nan"), dtype=torch.float64, device="cuda")
+    _noalloc_device(lat)          # first call on this GPU looks up the scratch array's address
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=lat._torch_stream, capture_error_mode="thread_local"):
+        st = lat.lib.lbm_diagnostics_noalloc(lat.ctx, ctypes.c_void_p(out.data_ptr()))
+    assert st == 0, lbm.last_error()
+    for k in range(4):
+        lat.lbm_step(2)
+        lat.lbm_synchronize()
+        _noalloc_device(other)    # the shared array now holds another context's partial sums
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        ref = lat.lbm_diagnostics()
+        print("replay %d: %s" % (k, got))
+        assert np.array_equal(got, ref), (k, got, ref)
