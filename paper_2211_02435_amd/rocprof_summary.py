@@ -161,21 +161,27 @@ def memory_view(dbs, copy_bytes=None, clock_ghz=2.1, scales=None):
     return out
 
 
-def traffic(fetch_db, write_db, kernel, copy_bytes, workload, layout=None):
+def traffic(fetch_db, write_db, kernel, copy_bytes, workload, layout=None, last=None):
+    """HBM bytes per launch of the kernel matching `kernel`: the median over its dispatches
+    (with `last`, over its last `last` dispatches only: the timed region of a bench run whose
+    autotuner launched the same kernel in other shapes first)."""
     f = counter_per_dispatch(fetch_db, "FETCH_SIZE")
     w = counter_per_dispatch(write_db, "WRITE_SIZE")
 
-    def pick(d, sub):
+    def pick(d, sub, n=None):
         vals = [v for k, vs in d.items() if sub in k for v in vs]
         if not vals:
             raise SystemExit("no dispatch of a kernel matching %r" % sub)
+        if n:
+            vals = vals[-n:]
         vals.sort()
         return vals[len(vals) // 2]  # median over dispatches
 
     f_copy, w_copy = pick(f, "copy_kernel"), pick(w, "copy_kernel")
-    f_k, w_k = pick(f, kernel), pick(w, kernel)
+    f_k, w_k = pick(f, kernel, last), pick(w, kernel, last)
     sf, sw = copy_bytes / (f_copy * 1024.0), copy_bytes / (w_copy * 1024.0)
-    return {"workload": workload, "layout": layout, "kernel_match": kernel, "kernel_source_sha": kernel_source_hash(),
+    return {"workload": workload, "layout": layout, "kernel_match": kernel, "last_dispatches": last,
+            "kernel_source_sha": kernel_source_hash(),
             "fetch_kib_per_launch_raw": f_k, "write_kib_per_launch_raw": w_k,
             "copy_fetch_kib_raw": f_copy, "copy_write_kib_raw": w_copy, "copy_bytes_each_way": copy_bytes,
             "fetch_scale": sf, "write_scale": sw,
@@ -198,6 +204,7 @@ def main(argv=None):
     t.add_argument("--workload", required=True)
     t.add_argument("--layout", default=None, help="storage layout of the profiled run (planes / rows)")
     t.add_argument("--out", default=None)
+    t.add_argument("--last", type=int, default=None, help="only the kernel's last N dispatches")
     c = sub.add_parser("counters")
     c.add_argument("dbs", nargs="+")
     c.add_argument("--match", default=None)
@@ -229,7 +236,7 @@ def main(argv=None):
             for n in sorted(vals):
                 print("    %-40s %20.1f" % (n, vals[n]))
     else:
-        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload, a.layout)
+        res = traffic(a.fetch, a.write, a.kernel, a.copy_bytes, a.workload, a.layout, a.last)
         txt = json.dumps(res, indent=1)
         if a.out:
             with open(a.out, "w") as f:
