@@ -85,21 +85,23 @@ def test_d3q27_cumulant_512_three_steps_sampled(storage, streaming, tol):
     assert err <= tol
 
 
-def test_d3q27_512_streaming_only_sweeps_move_populations_exactly():
-    """The pull index maps at the metric size in the metric launch (blocks of 256 x 1 threads,
-    XCD order, 53248 bytes of LDS reserved, rows layout, FP32): 20 sweeps with the collision
-    replaced by the identity (lbm_debug_stream_only) must leave df_i(x, 20) = df_i(x - 20 xi_i, 0)
-    bit for bit at every sampled cell, box faces and corners included."""
+@pytest.mark.parametrize("storage,bx", [("f32", 256), ("f64", 128)])
+def test_d3q27_512_streaming_only_sweeps_move_populations_exactly(storage, bx):
+    """The pull index maps at the metric size in the metric launches (blocks of 256 x 1 threads
+    for FP32 and 128 x 1 for FP64, XCD order, 53248 bytes of LDS reserved, rows layout): 20
+    sweeps with the collision replaced by the identity (lbm_debug_stream_only) must leave
+    df_i(x, 20) = df_i(x - 20 xi_i, 0) bit for bit at every sampled cell, box faces and corners
+    included."""
     import torch
     cfg = W.WORKLOADS["d3q27_cumulant_512"]
     n = cfg["dims"][0]
     steps = 20
     om = O.regularized_rates("D3Q27", cfg["omega_shear"])
     rho, u = W.tgv3d_fields(n, u0=cfg["u0"])
-    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, n), storage="f32")
+    lat = lbm.Lattice("D3Q27", "cumulant", om, (n, n, n), storage=storage)
     lat.lbm_init_equilibrium(rho, u)
     del rho, u
-    lat.lbm_set_launch(256, 1, 1)
+    lat.lbm_set_launch(bx, 1, 1)
     lat.lbm_set_lds_reserve(53248)
     pts = W.sample_cells((n, n, n), 512, seed=8)
     c = np.asarray(O.stencil("D3Q27").xi, dtype=np.int64)  # (q, 3)
@@ -118,8 +120,8 @@ def test_d3q27_512_streaming_only_sweeps_move_populations_exactly():
     got = _gpu_samples(lat, pts)
     lat.close()
     mism = int((got != want).sum())
-    print("D3Q27 512^3 FP32, %d streaming-only sweeps, %d sampled cells: %d mismatches"
-          % (steps, len(pts), mism))
+    print("D3Q27 512^3 %s, %d streaming-only sweeps, %d sampled cells: %d mismatches"
+          % (storage, steps, len(pts), mism))
     assert mism == 0
 
 
