@@ -311,3 +311,48 @@ def test_d2q9_macroscopic_zeroes_the_z_velocity_on_the_host_path():
     lbm.check(lat.lib.lbm_macroscopic(lat.ctx, lbm._dptr(r), lbm._dptr(v)))
     assert np.all(v[2] == 0.0)
     assert np.all(np.isfinite(v))
+
+
+def test_contexts_stepped_from_two_host_threads_match_sequential_runs():
+    """Two contexts (different stencils, spaces and streaming patterns, each on its own stream)
+    stepped at the same time from two host threads, each capturing and replaying its own
+    graphs, give bit for bit the states of the same runs made one after the other."""
+    import threading
+    specs = [("D3Q27", "cumulant", "pull", (70, 9, 5), 3), ("D3Q19", "raw", "aa", (40, 12, 10), 4)]
+
+    def make(spec):
+        stencil, space, streaming, dims, seed = spec
+        om = _general(stencil, seed=seed)
+        m = O.Method(stencil, space, om)
+        lat = lbm.Lattice(stencil, space, om, dims, storage="f32", streaming=streaming)
+        lat.lbm_set_populations(_state(m, dims, seed=seed))
+        return lat
+
+    ref = []
+    for spec in specs:
+        lat = make(spec)
+        lat.lbm_step(300)
+        ref.append(lat.lbm_get_populations())
+        lat.close()
+    lats = [make(spec) for spec in specs]
+    errors = []
+
+    def run(lat):
+        try:
+            for _ in range(6):
+                lat.lbm_step(50)
+            lat.lbm_synchronize()
+        except Exception as e:  # reported in the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=run, args=(lat,)) for lat in lats]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=120)
+    assert not any(t.is_alive() for t in threads)
+    assert not errors, errors
+    for lat, want in zip(lats, ref):
+        assert lat.lbm_time() == 300
+        np.testing.assert_array_equal(lat.lbm_get_populations(), want)
+        lat.close()
