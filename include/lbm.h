@@ -222,7 +222,9 @@ lbm_status lbm_validate(const lbm_params *p);
 lbm_status lbm_required_bytes(const lbm_params *p, size_t *bytes);
 
 /* Create a context: validate, derive the relaxation matrix in monomial form, allocate or
- * attach device buffers, pick the launch shape.  *out is NULL on failure. */
+ * attach device buffers, pick the launch shape.  *out is NULL on failure.  LBM_ENOMEM when
+ * the buffers the library allocates exceed the free device memory (checked with
+ * hipMemGetInfo before any allocation is attempted) or a caller buffer is too small. */
 lbm_status lbm_create(const lbm_params *p, lbm_ctx **out);
 void lbm_destroy(lbm_ctx *ctx);
 
@@ -380,7 +382,8 @@ typedef struct lbm_batch lbm_batch;
 
 /* common: stencil, space, equilibrium, eq_form, storage, streaming (pull only), stream;
  * its dims, omegas and buffers are ignored.  dims: nboxes * 3 (nx, ny, nz);
- * omegas: nboxes * q rates.  3-D stencils only. */
+ * omegas: nboxes * q rates.  3-D stencils only.  LBM_ENOMEM when the two population arrays
+ * exceed the free device memory (checked before allocating). */
 lbm_status lbm_batch_create(const lbm_params *common, int nboxes, const int64_t *dims,
                             const double *omegas, lbm_batch **out);
 void lbm_batch_destroy(lbm_batch *b);

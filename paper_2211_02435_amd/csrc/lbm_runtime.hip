@@ -99,6 +99,20 @@ static lbm_status hip_fail(hipError_t e, const char *what) {
     if (e_ != hipSuccess) return hip_fail(e_, what); \
   } while (0)
 
+// Population buffers larger than the free device memory are refused with LBM_ENOMEM before
+// hipMalloc is asked for them: an allocation beyond the device's memory is reported by the HIP
+// runtime as a missing device and leaves the process unable to create streams afterwards.
+static lbm_status check_free_memory(size_t need, const char *what) {
+  size_t free_b = 0, total_b = 0;
+  const hipError_t e = hipMemGetInfo(&free_b, &total_b);
+  if (e != hipSuccess) return hip_fail(e, "device memory query");
+  if (need > free_b)
+    return fail(LBM_ENOMEM, std::string(what) + " allocation needs " + std::to_string(need) + " bytes, " +
+                                std::to_string(free_b) + " of " + std::to_string(total_b) +
+                                " bytes of device memory are free");
+  return LBM_OK;
+}
+
 static bool is_device_ptr(const void *p) {
   if (!p) return false;
   hipPointerAttribute_t a;
@@ -536,6 +550,18 @@ extern "C" lbm_status lbm_create(const lbm_params *p, lbm_ctx **out) {
     c->L.ys = uint32_t(ys);
     c->layout = resolve_layout(p);
     c->buf_bytes = size_t(elems) * c->elem;
+  }
+  {
+    size_t need = 0;
+    for (int k = 0; k < c->nbuf; ++k)
+      if (!p->buffers[k]) need += c->buf_bytes;
+    if (need) {
+      s = check_free_memory(need, "population buffer");
+      if (s != LBM_OK) {
+        delete c;
+        return s;
+      }
+    }
   }
   for (int k = 0; k < c->nbuf; ++k) {
     if (p->buffers[k]) {
@@ -1547,6 +1573,10 @@ extern "C" lbm_status lbm_batch_create(const lbm_params *common, int nboxes, con
   };
   hipError_t e;
   const size_t plane_bytes = size_t(b->ntot) * b->elem, buf_bytes = plane_bytes * b->q;
+  if (lbm_status sm = check_free_memory(2 * buf_bytes, "population buffer"); sm != LBM_OK) {
+    lbm_batch_destroy(b);
+    return sm;
+  }
   for (int k = 0; k < 2; ++k) {
     e = hipMalloc(&b->buf[k], buf_bytes);
     if (e != hipSuccess) return bail(e, "population buffer allocation");

@@ -126,11 +126,18 @@ _lib = None
 
 
 def load():
-    """Load the HIP library; raises if it has not been built (there is no fallback)."""
+    """Load the HIP library; raises if it has not been built (there is no fallback).
+
+    PyTorch is imported first.  Its ROCm build carries its own HIP runtime, which its libraries
+    request under another file name than the library's dependency; loaded first, the library
+    would pull in the system runtime and torch would then add its own, leaving two HIP runtimes
+    (and two HSA runtimes) in the process, and the one initialised second reports no device.
+    Imported first, torch's runtime is the one the library binds to."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libpaper_lbm.so not found at %s; build it with __graft_entry__.build()" % LIB_PATH)
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(lib, name)

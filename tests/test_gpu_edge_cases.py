@@ -14,6 +14,8 @@
 
 Bars: FP64 max |df_gpu - df_oracle| <= 1e-13 after 5 steps from a non-equilibrium state.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -217,3 +219,50 @@ def test_largest_z_plane_two_steps_sampled(storage, dims, tol, streaming):
     print("D3Q27 %s %s, z-plane of %d bytes, two steps, %d sampled cells: max|d df| = %.3e"
           % (storage, dims, plane, len(pts), err))
     assert err <= tol
+
+
+def test_allocation_failure_reports_enomem_and_leaves_the_device_usable():
+    """A box that passes validation but needs more device memory than the GPU holds (2^31
+    D3Q27 cells in FP64 with two library-owned buffers, 2 x 464 GB): lbm_create compares the
+    request with the free device memory before allocating and returns LBM_ENOMEM with both
+    sizes in the message; a context created afterwards steps and matches the oracle."""
+    om = O.regularized_rates("D3Q27", 1.9)
+    big = (2048, 2048, 512)
+    assert lbm.lbm_validate(lbm.make_params("D3Q27", "cumulant", om, big, storage="f64")) == 0
+    with pytest.raises(lbm.LbmError) as err:
+        lbm.Lattice("D3Q27", "cumulant", om, big, storage="f64", torch_buffers=False)
+    print("lbm_create of %s FP64: %s" % (big, err.value))
+    assert err.value.status == lbm.LBM_ENOMEM
+    assert "bytes of device memory are free" in str(err.value)
+    dims = (20, 12, 9)
+    m = O.Method("D3Q27", "cumulant", om)
+    df0 = _state(m, dims, seed=31)
+    lat = lbm.Lattice("D3Q27", "cumulant", om, dims, storage="f64", torch_buffers=False)
+    lat.lbm_set_populations(df0)
+    lat.lbm_step(5)
+    err = np.abs(lat.lbm_get_populations() - O.step(m, df0, 5)).max()
+    lat.close()
+    assert err <= 1e-13
+
+
+def test_library_loaded_before_torch_shares_its_runtime(tmp_path):
+    """A fresh process that loads the library (through a host-only call) before it imports
+    torch, then creates a context with library-owned buffers and steps it: the binding imports
+    torch before loading the library, so one HIP runtime serves both."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2211_02435_amd import lbm\n"
+        "import oracle as O\n"
+        "om = O.regularized_rates('D3Q27', 1.9)\n"
+        "assert lbm.lbm_validate(lbm.make_params('D3Q27', 'cumulant', om, (16, 16, 16))) == 0\n"
+        "lat = lbm.Lattice('D3Q27', 'cumulant', om, (16, 16, 16), storage='f64', torch_buffers=False)\n"
+        "lat.lbm_init_equilibrium(*__import__('lbm_workloads').tgv3d_fields(16, u0=0.05))\n"
+        "lat.lbm_step(3)\n"
+        "print('ok', lat.lbm_time())\n" % root)
+    print("fresh process: library loaded before torch", flush=True)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300, cwd=root)
+    assert r.returncode == 0, (r.returncode, r.stdout, r.stderr[-2000:])
+    assert r.stdout.split()[-2:] == ["ok", "3"]
