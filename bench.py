@@ -524,10 +524,13 @@ def main():
         print("[bench] accuracy vs oracle: %s" % json.dumps(accuracy), file=sys.stderr, flush=True)
 
     r = runs[main_st]
+    cells = int(np.prod(dims))
     plain = (n == cfg["dims"][0] and args.streaming == "pull" and args.transform == "chimera"
              and args.rates == "regularized" and not args.launch)
     if "f64" in runs and main_st != "f64":
         runs["f64"]["traffic"] = measured_traffic(name, runs["f64"].get("layout"), "f64") if plain else None
+        runs["f64"]["traffic_bytes_per_lup"] = runs["f64"]["traffic"] / cells if runs["f64"]["traffic"] else None
+    traffic = measured_traffic(name, r.get("layout"), main_st) if plain else None
     fields_desc = ("shallow water g 0.1, 16 Gaussian bumps" if name == "swe_d2q9_4096"
                    else "Taylor-Green u0 %.2f" % cfg["u0"])
     workload = "%s %s %s periodic, %s, omega_s %.6f, %s, %s" % (
@@ -547,13 +550,14 @@ def main():
         "vs_baseline": None,
         "dtype": main_st,
         "data": "synthetic initial fields (Taylor-Green vortex / Gaussian water bumps)",
-        "config": {"workload": workload, "cells": int(np.prod(dims)), "storage": main_st,
+        "config": {"workload": workload, "cells": cells, "storage": main_st,
                    "layout": r.get("layout", args.layout), "streaming": args.streaming, "transform": args.transform,
                    "rates": args.rates,
                    "launch_bx_by_swizzle_variant_lds": r["launch_bx_by_swizzle_variant_lds"]},
         "roofline": {"bound": "hbm", "achieved": r["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r["frac"],
-                     "traffic": measured_traffic(name, r.get("layout"), main_st) if plain else None,
+                     "traffic": traffic,
+                     "traffic_bytes_per_lup": traffic / cells if traffic else None,
                      "kernel": "sweep_kernel<%s, %s, %s, %s, %s>" % (cfg["stencil"], cfg["space"], args.rates,
                                                                      main_st, args.streaming),
                      "bytes_per_lup": r["bytes_per_lup"], "avg_launch_ms": r["avg_launch_ms"]},
